@@ -1,0 +1,176 @@
+"""Benchmark of the colour-gradient LBM time step on one MI355X.
+
+Workload: D3Q19 drainage in a synthetic rock, single precision, MRT: a 256^3
+voxel box made from a seeded Gaussian random field (correlation length 8)
+thresholded to porosity 0.22 in the rock region with the spanning pore cluster
+kept, ten pure-fluid layers at each end and solid side walls, initially
+wetting-saturated, non-wetting fluid injected at z = 0 by a Zou-He inlet with
+rho_in - rho_out = 0.02, theta = 30 deg (Scheme-I), tau_r = 1.0, tau_b = 0.6,
+sigma = 0.01, beta = 0.95.
+
+One step = the whole step (phase field, both extrapolations, normals with
+wetting, and the fused stream-collide-recolour kernel) over all fluid nodes.
+Prints one JSON line: MLUPS counted over fluid nodes (value) and over all
+voxels, the HBM roofline of the dominant kernel from HIP events in the timed
+region, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+B_ALG_F32_D3Q19 = 2 * 19 * 2 * 4  # two colours x Q x (read + write) x 4 bytes = 304
+
+
+def workload(n=256):
+    from paper_2407_10914_amd import inputs
+
+    case = inputs.grf_rock(n=n, corr=8.0, porosity=0.22, seed=inputs.MASTER_SEED, buffer=10)
+    kw = dict(dim=3, periodic=case.periodic, tau_r=1.0, tau_b=0.6, sigma=0.01, beta=0.95, scheme=1,
+              theta_deg=30.0, bc=1, rho_in=1.02, rho_out=1.0, zeta_r=1.0, collision=1)
+    return case, kw
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2407_10914_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip", ".cpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n_fluid):
+    """HBM bytes per k_main launch from the committed rocprofv3 PMC summary,
+    or None when missing or taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "k_main_rock256_f32_pmc.md")
+    if not os.path.exists(path):
+        return None
+    meta = {}
+    for line in open(path):
+        if line.startswith("<!--") and "traffic:" in line:
+            body = line.strip()[4:-3].split("traffic:", 1)[1]
+            meta = json.loads(body)
+    if not meta or meta.get("kernel_hash") != kernel_source_hash() or meta.get("n_fluid") != n_fluid:
+        return None
+    return meta.get("bytes_per_launch")
+
+
+def cpu_baseline(case, kw, budget_s=20.0):
+    """The CPU oracle on the same 256^3 rock: setup untimed, then whole steps
+    until about budget_s seconds of stepping (at least one)."""
+    import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = O.OracleSim(case.solid, eps="f32", **kw)
+    o.set_phase(case.phi0)
+    n_fluid = int((case.solid == 0).sum())
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / steps * (steps + 1) > 1.5 * budget_s:
+            break
+    return dict(value=n_fluid * steps / el / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{steps} step(s) of the same 256^3 rock (FP64 oracle, {n_fluid} fluid nodes), "
+                       f"{el:.1f} s, OpenMP threads={threads}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the step runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2407_10914_amd.sim import Sim
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    case, kw = workload(args.n)
+    sim = Sim(case.solid, precision="f32", **kw)
+    sim.set_phase(case.phi0)
+    info = sim.info()
+    n_fluid = info["fluid"]
+    print(f"# setup {time.perf_counter() - t_setup:.1f} s, fluid nodes {n_fluid}, voxels {info['voxels']}",
+          file=sys.stderr, flush=True)
+
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    sim.set_timing(["k_main"])
+    sim.reset_timing()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kt = sim.kernel_times()
+    sim.set_timing(None)
+    main_n, main_ms = kt["k_main"]
+    obs = sim.observe(axis=2, plane=args.n // 2)
+    ms_per_step = gpu_ms / args.steps
+    mlups = n_fluid * args.steps / (gpu_ms / 1e3) / 1e6
+    vox_mlups = info["voxels"] * args.steps / (gpu_ms / 1e3) / 1e6
+    main_avg_s = main_ms / max(main_n, 1) / 1e3
+    achieved = B_ALG_F32_D3Q19 * n_fluid / main_avg_s / 1e9
+    traffic = read_traffic(n_fluid)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_main",
+            "bytes_alg_per_launch": B_ALG_F32_D3Q19 * n_fluid, "avg_launch_us": round(main_avg_s * 1e6, 2)}
+    step_frac = mlups * 1e6 * B_ALG_F32_D3Q19 / (HBM_PEAK_GBS * 1e9)
+    del sim
+    torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(case, kw)
+    line = {
+        "metric": "MLUPS D3Q19 color-gradient 256^3",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 two-phase drainage, synthetic Gaussian-random-field rock {args.n}^3, "
+                               "porosity 0.22, Zou-He drho=0.02, Scheme-I 30 deg, MRT, FP32",
+                   "fluid_nodes": n_fluid, "voxels": info["voxels"], "voxel_mlups": round(vox_mlups, 1),
+                   "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3),
+                   "sat_nw_mass": obs["sat_nw_mass"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * cg_lbm.h - C ABI of the MI355X (gfx950) colour-gradient lattice Boltzmann
+ * library libcglbm.so.
+ *
+ * The library advances the two-colour lattice Boltzmann model of Sedahmed &
+ * Coelho, arXiv:2407.10914 (Sec. II; the model of their Ref. [20]):
+ *   - lattices: D3Q19 (Appendix A, Eqs. A.1-A.2) and D2Q9 (the in-plane
+ *     subset of D3Q19, same order);
+ *   - collision on the total distribution: MRT (Eqs. 2-4, A.3-A.5, D3Q19) or
+ *     single-relaxation-time BGK, both with Guo forcing, local rates from the
+ *     harmonic-mean viscosity (Eqs. 13-16);
+ *   - continuum-surface-force tension F = 1/2 sigma kappa C (Eq. 5) with the
+ *     isotropic colour gradient (Eq. 6) and curvature (Eq. 12);
+ *   - Latva-Kokko recolouring (Eqs. 20-21);
+ *   - wetting Scheme-I (secant, Eqs. 28-31) or Scheme-II (Eqs. 32-33) with the
+ *     wall normal from the smoothed image (Eqs. 25-26), the phase field and
+ *     the normal extrapolated into the solid boundary points (Eqs. 34-35),
+ *     applied in the order of Sec. II.B.3;
+ *   - pull streaming with halfway bounce-back at solid links;
+ *   - Type-I Zou-He pressure inlet (z = 0) / outlet (z = nz-1) faces
+ *     (Appendix B, with the injected fluid of Sec. II.D.1 and the outlet rule
+ *     of Eq. 39) and/or a Type-II uniform body force (Eq. 36).
+ *
+ * Conventions shared by every call:
+ *   - lattice units: dx = dt = c = 1, c_s^2 = 1/3;
+ *   - voxel arrays are dense over nx*ny*nz, x fastest: v = x + nx*(y + ny*z);
+ *     population arrays are [Q][V]; vector fields are [3][V];
+ *   - the state at time t is the set of pre-collision populations f^r_i, f^b_i
+ *     at the fluid voxels (left-hand side of Eq. 1 after streaming and the
+ *     Zou-He faces);
+ *   - every pointer argument is owned by the caller; the library copies what it
+ *     needs before returning, except where a call says otherwise;
+ *   - calls return CG_OK (0) or a negative cg_status; cg_last_error() returns a
+ *     thread-local message for the last failure on the calling thread;
+ *   - a handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef CG_LBM_H
+#define CG_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CG_OK = 0,
+  CG_EINVAL = -1,       /* bad argument or inconsistent geometry */
+  CG_ENOMEM = -2,       /* device or host allocation failed */
+  CG_EHIP = -3,         /* a HIP runtime call failed */
+  CG_EUNSTABLE = -4,    /* NaN/Inf found in the state */
+  CG_EUNSUPPORTED = -5, /* valid but not implemented combination */
+  CG_ESTATE = -6        /* call not valid in the handle's current state */
+} cg_status;
+
+/* Geometry: solid[v] = 1 for a solid voxel, 0 for fluid (the binary matrix of
+ * Sec. II.B.1).  dim = 2 requires nz = 1.  An axis is periodic or, when the
+ * boundary type is CG_BC_ZOUHE, the z axis is open; on every other axis the
+ * first and last layers must be solid. */
+typedef struct {
+  int dim;
+  int nx, ny, nz;
+  const uint8_t* solid;
+  uint8_t periodic[3];
+} cg_geometry;
+
+enum { CG_WET_NONE = 0, CG_WET_SCHEME1 = 1, CG_WET_SCHEME2 = 2 };
+/* Scheme-I secant start: SIGN_RULE takes v1 = n_c - (n_c + s n_w)/2 with
+ * s = +1 for theta > 90 deg and s = -1 otherwise; LITERAL keeps s = +1 (Eq. 30
+ * as printed). */
+enum { CG_S1_SIGN_RULE = 0, CG_S1_LITERAL = 1 };
+
+/* Wetting (Sec. II.B).  theta_deg is the contact angle measured through fluid
+ * b.  theta_field_deg, when not NULL, gives a per-voxel angle on the solid
+ * voxels (dense, V entries; fluid entries ignored); a fluid boundary node then
+ * takes the w_i-weighted mean over its solid link neighbours. */
+typedef struct {
+  int scheme;
+  double theta_deg;
+  const double* theta_field_deg;
+  int scheme1_line;
+} cg_wetting;
+
+enum { CG_BC_NONE = 0, CG_BC_ZOUHE = 1 };
+/* Driving (Sec. II.C).  CG_BC_ZOUHE opens the z faces: a per-colour Zou-He
+ * inlet at z = 0 with density rho_in and red fraction zeta_r (Eqs. B.1-B.8;
+ * the injected phase is phi_in = zeta_r - (1 - zeta_r)) and a Zou-He outlet at
+ * z = nz-1 with density rho_out (Eqs. B.9-B.18, phi of Eq. 39).  g is the
+ * body-force acceleration of Eq. (36), applied as force density rho_o g at
+ * every fluid node; it may be combined with either type.  Type-I driving is
+ * CG_BC_ZOUHE with rho_in > rho_out and g = 0; Type-II is a g along z with
+ * rho_in = rho_out (or a periodic z axis). */
+typedef struct {
+  int type;
+  double rho_in, rho_out, zeta_r;
+  double g[3];
+} cg_bc;
+
+enum { CG_FP32 = 0, CG_FP64 = 1 };
+enum { CG_BGK = 0, CG_MRT = 1 };
+
+typedef void* (*cg_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*cg_free_fn)(void* ptr, void* ctx);
+
+/* Options.  precision: CG_FP64 evaluates every operation in the order of the
+ * reference definition without fused multiply-adds; CG_FP32 stores a compact
+ * post-collision state (total populations as deviations from w_i rho0, plus
+ * the recolouring coefficients) and computes in single precision.  eps_c: |C| below which
+ * the interface normal is zero (Eq. 27 guard); eps_f, eps_v: Scheme-I/II
+ * guards.  stream: a hipStream_t (NULL = the default stream).  alloc/free: an
+ * optional device allocator (for example the PyTorch caching allocator); NULL
+ * uses hipMalloc/hipFree.  block: threads per block for the node kernels
+ * (0 = default). */
+typedef struct {
+  int precision;
+  int collision;
+  double rho0;
+  double eps_c, eps_f, eps_v;
+  int device;
+  void* stream;
+  cg_alloc_fn alloc;
+  cg_free_fn free;
+  void* alloc_ctx;
+  int block;
+} cg_options;
+
+/* Fill *opt with the defaults for the given precision: MRT, rho0 = 1,
+ * eps_c = 1e-6, eps_f = eps_v = 1e-12 (FP64) or 1e-6 (FP32), device 0,
+ * default stream, hipMalloc, default block. */
+void cg_options_default(cg_options* opt, int precision);
+
+typedef struct cg_lbm cg_lbm;
+
+/* Create a run.  tau_r, tau_b > 1/2 (Eq. 13), 0 <= beta <= 1 (Eq. 17),
+ * 0 < theta < 180 when a scheme is set.  Performs the once-per-run setup on
+ * the host (voxel classes, boundary sets F_b and S_b along lattice links,
+ * three smoothing passes and the wall normal of Eqs. 25-26 in FP64, the
+ * sparse fluid-node index and pull table), uploads it, and leaves the state
+ * at rest with phi = -1 (all fluid b).  Errors: CG_EINVAL, CG_EUNSUPPORTED
+ * (MRT or Zou-He with dim = 2), CG_ENOMEM, CG_EHIP.  *out receives the handle. */
+cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, double sigma, double beta,
+                        const cg_wetting* wet, const cg_bc* bc, const cg_options* opt, cg_lbm** out);
+
+/* Free everything the handle owns (synchronises its stream first). */
+void cg_lbm_destroy(cg_lbm* h);
+
+/* Thread-local message of the last failure. */
+const char* cg_last_error(void);
+
+/* Initial state at rest: f^s_i = w_i rho^s with rho^r = rho0 (1 + phi)/2 and
+ * rho^b = rho0 (1 - phi)/2 at every fluid voxel.  phi0: host, V doubles. */
+cg_status cg_lbm_set_phase(cg_lbm* h, const double* phi0);
+
+/* Set the state: canonical pre-collision populations fr, fb ([Q][V] doubles,
+ * solid entries ignored), host or device memory. */
+cg_status cg_lbm_set_state(cg_lbm* h, const double* fr, const double* fb, int src_is_device);
+
+/* Enqueue n time steps on the handle's stream; returns without waiting. */
+cg_status cg_lbm_step(cg_lbm* h, int64_t n);
+
+/* Wait for the handle's stream. */
+cg_status cg_lbm_sync(cg_lbm* h);
+
+/* Number of completed steps. */
+int64_t cg_lbm_time(const cg_lbm* h);
+
+typedef struct {
+  int64_t step;
+  double mass_r, mass_b;        /* sum of rho^r, rho^b over fluid nodes (FP64 accumulation) */
+  double n_fluid;               /* fluid nodes counted (finite ones) */
+  double sat_w;                 /* #{phi < 0} / #fluid (Sec. IV.B) */
+  double sat_nw_mass;           /* sum rho^r / sum rho */
+  double flux_t, flux_r, flux_b;/* sum of rho u_a, rho^r u_a, rho^b u_a over the plane */
+  double vol_r, vol_b;          /* sum (1 + phi)/2, sum (1 - phi)/2 */
+  double p_in, p_out;           /* mean rho/3 (Eq. 23) over phi > 0.9 / phi < -0.9 */
+  double n_in, n_out;
+  double u_max;                 /* max |u| (Eq. 22) */
+  double nan_count;             /* fluid nodes with a non-finite density or velocity */
+} cg_observables;
+
+/* Reductions over the current state (wavefront shuffles, then a fixed-order
+ * second pass); axis/plane choose the flux plane (axis < 0: no flux).
+ * Synchronises the stream.  Returns CG_EUNSTABLE if nan_count > 0 (out is
+ * still filled). */
+cg_status cg_lbm_observe(cg_lbm* h, int axis, int plane, cg_observables* out);
+
+enum {
+  CG_FIELD_RHO_R = 0, /* [V] */
+  CG_FIELD_RHO_B = 1, /* [V] */
+  CG_FIELD_PHI = 2,   /* [V] phase field at fluid nodes and solid boundary points */
+  CG_FIELD_U = 3,     /* [3][V] velocity, Eq. (22) */
+  CG_FIELD_F_R = 4,   /* [Q][V] canonical pre-collision red populations */
+  CG_FIELD_F_B = 5,   /* [Q][V] canonical pre-collision blue populations */
+  CG_FIELD_N = 6,     /* [3][V] interface normal after wetting, fluid and S_b */
+  CG_FIELD_C = 7,     /* [3][V] colour gradient after wetting, fluid */
+  CG_FIELD_KAPPA = 8, /* [V] curvature, Eq. (12) */
+  CG_FIELD_FORCE = 9  /* [3][V] total force, Eq. (5) plus rho_o g */
+};
+
+/* Copy a field of the current state into dst (doubles, dense; entries where
+ * the field is undefined are 0).  dst_is_device: dst is device memory on the
+ * handle's device.  Synchronises the stream. */
+cg_status cg_lbm_get_field(cg_lbm* h, int which, double* dst, int dst_is_device);
+
+typedef struct {
+  int dim, q, nx, ny, nz, precision, collision;
+  int64_t voxels, fluid, fluid_boundary, solid_boundary, inlet, outlet;
+  int64_t state_bytes;   /* bytes of one state copy on the device */
+  int64_t device_bytes;  /* all device memory owned by the handle */
+} cg_info;
+
+cg_status cg_lbm_info(const cg_lbm* h, cg_info* out);
+
+/* Opaque device-state snapshot (checkpoint / resume, bitwise).  dst/src are
+ * host buffers of cg_info.state_bytes + 64 bytes. */
+int64_t cg_lbm_snapshot_bytes(const cg_lbm* h);
+cg_status cg_lbm_save(cg_lbm* h, void* dst);
+cg_status cg_lbm_load(cg_lbm* h, const void* src);
+
+/* Kernel timing: mask selects the kernels of cg_lbm_step whose every launch is
+ * bracketed by HIP events on the handle's stream (bit k = k-th kernel in the
+ * order cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n,
+ * k_main; -1 = all, 0 = off).  cg_lbm_kernel_times synchronises, then reports
+ * for each kernel its name, launch count and total milliseconds since the
+ * last reset (n: in = capacity, out = count). */
+cg_status cg_lbm_set_timing(cg_lbm* h, int mask);
+cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n);
+cg_status cg_lbm_reset_timing(cg_lbm* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CG_LBM_H */

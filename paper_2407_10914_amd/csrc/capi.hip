@@ -1,0 +1,335 @@
+// C ABI of libcglbm.so (declarations and contracts in include/cg_lbm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "../../include/cg_lbm.h"
+#include "engine_base.hpp"
+#include "setup.hpp"
+
+namespace {
+thread_local std::string g_err;
+cg_status fail(cg_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+}  // namespace
+
+struct cg_lbm {
+  cg::HostSetup S;
+  cg::StepParams P{};
+  cg::Alloc al;
+  std::unique_ptr<cg::EngineBase> eng;
+  hipStream_t stream = nullptr;
+  int device = 0, precision = CG_FP32, collision = CG_MRT;
+};
+
+namespace {
+
+cg_status engine_status(cg_lbm* h, int rc) {
+  if (rc == CG_OK) return CG_OK;
+  return fail((cg_status)rc, h->eng->err_.empty() ? std::string("device engine error") : h->eng->err_);
+}
+
+struct DevTemp {
+  cg_lbm* h;
+  double* p = nullptr;
+  size_t bytes = 0;
+  DevTemp(cg_lbm* h_, size_t b) : h(h_), bytes(b) { p = (double*)h->al.get(b); }
+  ~DevTemp() {
+    if (p) {
+      (void)hipStreamSynchronize(h->stream);
+      h->al.put(p);
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* cg_last_error(void) { return g_err.c_str(); }
+
+void cg_options_default(cg_options* opt, int precision) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = precision;
+  opt->collision = CG_MRT;
+  opt->rho0 = 1.0;
+  opt->eps_c = 1e-6;
+  opt->eps_f = precision == CG_FP64 ? 1e-12 : 1e-6;
+  opt->eps_v = precision == CG_FP64 ? 1e-12 : 1e-6;
+  opt->device = 0;
+  opt->block = 0;
+}
+
+cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, double sigma, double beta,
+                        const cg_wetting* wet, const cg_bc* bc, const cg_options* opt, cg_lbm** out) {
+  if (!out) return fail(CG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!geom || !geom->solid) return fail(CG_EINVAL, "geometry or solid mask is NULL");
+  cg_wetting w{};
+  if (wet) w = *wet;
+  cg_bc b{};
+  if (bc) b = *bc;
+  cg_options o;
+  if (opt)
+    o = *opt;
+  else
+    cg_options_default(&o, CG_FP32);
+  if (!(tau_r > 0.5) || !(tau_b > 0.5)) return fail(CG_EINVAL, "tau_r and tau_b must exceed 1/2");
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(CG_EINVAL, "beta must lie in [0, 1]");
+  if (!std::isfinite(sigma)) return fail(CG_EINVAL, "sigma must be finite");
+  if (w.scheme < 0 || w.scheme > 2) return fail(CG_EINVAL, "unknown wetting scheme");
+  if (w.scheme != 0 && !w.theta_field_deg && !(w.theta_deg > 0.0 && w.theta_deg < 180.0))
+    return fail(CG_EINVAL, "theta must lie in (0, 180) degrees");
+  if (b.type != CG_BC_NONE && b.type != CG_BC_ZOUHE) return fail(CG_EINVAL, "unknown boundary type");
+  if (b.type == CG_BC_ZOUHE && !(b.zeta_r >= 0.0 && b.zeta_r <= 1.0))
+    return fail(CG_EINVAL, "zeta_r must lie in [0, 1]");
+  if (o.precision != CG_FP32 && o.precision != CG_FP64) return fail(CG_EINVAL, "unknown precision");
+  if (o.collision != CG_BGK && o.collision != CG_MRT) return fail(CG_EINVAL, "unknown collision");
+  if (geom->dim == 2 && o.collision == CG_MRT) return fail(CG_EUNSUPPORTED, "MRT is defined for D3Q19 only");
+  if (geom->dim == 2 && b.type == CG_BC_ZOUHE) return fail(CG_EUNSUPPORTED, "Zou-He faces are defined for D3Q19");
+  if (!(o.rho0 > 0.0)) return fail(CG_EINVAL, "rho0 must be positive");
+  if (w.theta_field_deg) {
+    const long V = (long)geom->nx * geom->ny * geom->nz;
+    for (long v = 0; v < V; ++v)
+      if (geom->solid[v] && !(w.theta_field_deg[v] > 0.0 && w.theta_field_deg[v] < 180.0))
+        return fail(CG_EINVAL, "theta field must lie in (0, 180) degrees on solid voxels");
+  }
+
+  std::unique_ptr<cg_lbm> h(new cg_lbm());
+  h->device = o.device;
+  h->precision = o.precision;
+  h->collision = o.collision;
+  if (hipSetDevice(o.device) != hipSuccess) return fail(CG_EHIP, "hipSetDevice failed");
+  h->stream = (hipStream_t)o.stream;
+  h->al.fn = o.alloc;
+  h->al.fr = o.free;
+  h->al.ctx = o.alloc_ctx;
+  std::string err;
+  int rc = cg::build_setup(*geom, w, b, &h->S, &err);
+  if (rc != CG_OK) return fail((cg_status)rc, err);
+  const cg::HostSetup& S = h->S;
+  cg::StepParams& P = h->P;
+  P.nx = S.nx;
+  P.ny = S.ny;
+  P.nz = S.nz;
+  P.N = S.N;
+  P.Np = S.Np;
+  P.nsb = (int)S.sb_vox.size();
+  P.V = S.V;
+  for (int a = 0; a < 3; ++a) P.per[a] = S.per[a];
+  P.bc = b.type;
+  P.scheme = w.scheme;
+  P.collision = o.collision;
+  P.half_sigma = 0.5 * sigma;
+  P.beta = beta;
+  P.rho0 = o.rho0;
+  P.nu_r = (tau_r - 0.5) / 3.0;
+  P.nu_b = (tau_b - 0.5) / 3.0;
+  for (int a = 0; a < 3; ++a) P.rg[a] = o.rho0 * b.g[a];
+  if (geom->dim == 2) P.rg[2] = 0.0;
+  P.rin_r = b.rho_in * b.zeta_r;
+  P.rin_b = b.rho_in * (1.0 - b.zeta_r);
+  P.rho_in = b.rho_in;
+  P.rho_out = b.rho_out;
+  P.phi_in = b.zeta_r - (1.0 - b.zeta_r);
+  P.eps_c = o.eps_c;
+  P.eps_f = o.eps_f;
+  P.eps_v = o.eps_v;
+  P.flux_axis = -1;
+  P.flux_plane = 0;
+  h->eng.reset(o.precision == CG_FP64 ? cg::make_engine_f64() : cg::make_engine_f32());
+  rc = h->eng->init(S, P, o.block, &h->al, h->stream, &err);
+  if (rc != CG_OK) {
+    if (err.empty()) return engine_status(h.get(), rc);
+    return fail((cg_status)rc, err);
+  }
+  *out = h.release();
+  return CG_OK;
+}
+
+void cg_lbm_destroy(cg_lbm* h) { delete h; }
+
+cg_status cg_lbm_set_phase(cg_lbm* h, const double* phi0) {
+  if (!h || !phi0) return fail(CG_EINVAL, "NULL argument");
+  std::vector<double> pn(h->S.N);
+  for (int n = 0; n < h->S.N; ++n) pn[n] = phi0[h->S.node_vox[n]];
+  h->eng->t = 0;
+  return engine_status(h, h->eng->set_phase_nodes(pn.data()));
+}
+
+cg_status cg_lbm_set_state(cg_lbm* h, const double* fr, const double* fb, int src_is_device) {
+  if (!h || !fr || !fb) return fail(CG_EINVAL, "NULL argument");
+  return engine_status(h, h->eng->set_state_dense(fr, fb, src_is_device != 0));
+}
+
+cg_status cg_lbm_step(cg_lbm* h, int64_t n) {
+  if (!h || n < 0) return fail(CG_EINVAL, "bad argument");
+  return engine_status(h, h->eng->step(n));
+}
+
+cg_status cg_lbm_sync(cg_lbm* h) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(CG_EHIP, hipGetErrorString(hipGetLastError()));
+  return CG_OK;
+}
+
+int64_t cg_lbm_time(const cg_lbm* h) { return h ? h->eng->t : -1; }
+
+cg_status cg_lbm_observe(cg_lbm* h, int axis, int plane, cg_observables* out) {
+  if (!h || !out) return fail(CG_EINVAL, "NULL argument");
+  double o[cg::kObsN];
+  int rc = h->eng->observe(axis, plane, o);
+  if (rc != CG_OK) return engine_status(h, rc);
+  std::memset(out, 0, sizeof(*out));
+  out->step = h->eng->t;
+  out->mass_r = o[0];
+  out->mass_b = o[1];
+  out->n_fluid = o[2];
+  out->sat_w = o[2] > 0 ? o[3] / o[2] : 0.0;
+  out->sat_nw_mass = (o[0] + o[1]) > 0 ? o[0] / (o[0] + o[1]) : 0.0;
+  out->vol_r = o[4];
+  out->vol_b = o[5];
+  out->p_in = o[7] > 0 ? o[6] / o[7] : 0.0;
+  out->n_in = o[7];
+  out->p_out = o[9] > 0 ? o[8] / o[9] : 0.0;
+  out->n_out = o[9];
+  out->u_max = o[10];
+  out->nan_count = o[11];
+  out->flux_t = o[12];
+  out->flux_r = o[13];
+  out->flux_b = o[14];
+  if (o[11] > 0) return fail(CG_EUNSTABLE, "non-finite density or velocity in the state");
+  return CG_OK;
+}
+
+cg_status cg_lbm_get_field(cg_lbm* h, int which, double* dst, int dst_is_device) {
+  if (!h || !dst) return fail(CG_EINVAL, "NULL argument");
+  const size_t V = (size_t)h->S.V, Q = (size_t)h->S.Q;
+  size_t comps;
+  switch (which) {
+    case CG_FIELD_RHO_R:
+    case CG_FIELD_RHO_B:
+    case CG_FIELD_PHI:
+    case CG_FIELD_KAPPA:
+      comps = 1;
+      break;
+    case CG_FIELD_U:
+    case CG_FIELD_N:
+    case CG_FIELD_C:
+    case CG_FIELD_FORCE:
+      comps = 3;
+      break;
+    case CG_FIELD_F_R:
+    case CG_FIELD_F_B:
+      comps = Q;
+      break;
+    default:
+      return fail(CG_EINVAL, "unknown field");
+  }
+  const size_t bytes = sizeof(double) * comps * V;
+  std::unique_ptr<DevTemp> tmp;
+  double* d = dst;
+  if (!dst_is_device) {
+    tmp.reset(new DevTemp(h, bytes));
+    if (!tmp->p) return fail(CG_ENOMEM, "device temporary");
+    d = tmp->p;
+  }
+  if (hipMemsetAsync(d, 0, bytes, h->stream) != hipSuccess) return fail(CG_EHIP, "memset");
+  int rc = CG_OK;
+  switch (which) {
+    case CG_FIELD_RHO_R: rc = h->eng->macro(d, nullptr, nullptr, nullptr, nullptr, nullptr); break;
+    case CG_FIELD_RHO_B: rc = h->eng->macro(nullptr, d, nullptr, nullptr, nullptr, nullptr); break;
+    case CG_FIELD_U: rc = h->eng->macro(nullptr, nullptr, d, nullptr, nullptr, nullptr); break;
+    case CG_FIELD_KAPPA: rc = h->eng->macro(nullptr, nullptr, nullptr, d, nullptr, nullptr); break;
+    case CG_FIELD_FORCE: rc = h->eng->macro(nullptr, nullptr, nullptr, nullptr, d, nullptr); break;
+    case CG_FIELD_C: rc = h->eng->macro(nullptr, nullptr, nullptr, nullptr, nullptr, d); break;
+    case CG_FIELD_PHI: rc = h->eng->phi_grid(d); break;
+    case CG_FIELD_N: rc = h->eng->n_grid(d); break;
+    case CG_FIELD_F_R:
+    case CG_FIELD_F_B: {
+      DevTemp other(h, bytes);
+      if (!other.p) return fail(CG_ENOMEM, "device temporary");
+      rc = which == CG_FIELD_F_R ? h->eng->export_pops(d, other.p) : h->eng->export_pops(other.p, d);
+      break;
+    }
+  }
+  if (rc != CG_OK) return engine_status(h, rc);
+  if (!dst_is_device) {
+    if (hipMemcpyAsync(dst, d, bytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+      return fail(CG_EHIP, "copy to host");
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(CG_EHIP, "stream sync");
+  return CG_OK;
+}
+
+cg_status cg_lbm_info(const cg_lbm* h, cg_info* out) {
+  if (!h || !out) return fail(CG_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->dim = h->S.dim;
+  out->q = h->S.Q;
+  out->nx = h->S.nx;
+  out->ny = h->S.ny;
+  out->nz = h->S.nz;
+  out->precision = h->precision;
+  out->collision = h->collision;
+  out->voxels = h->S.V;
+  out->fluid = h->S.N;
+  out->fluid_boundary = h->S.n_fb;
+  out->solid_boundary = (int64_t)h->S.sb_vox.size();
+  out->inlet = h->S.n_in;
+  out->outlet = h->S.n_out;
+  out->state_bytes = (int64_t)h->eng->state_bytes();
+  out->device_bytes = (int64_t)h->eng->device_bytes();
+  return CG_OK;
+}
+
+int64_t cg_lbm_snapshot_bytes(const cg_lbm* h) { return h ? (int64_t)h->eng->snapshot_bytes() : -1; }
+
+cg_status cg_lbm_save(cg_lbm* h, void* dst) {
+  if (!h || !dst) return fail(CG_EINVAL, "NULL argument");
+  return engine_status(h, h->eng->save(dst));
+}
+
+cg_status cg_lbm_load(cg_lbm* h, const void* src) {
+  if (!h || !src) return fail(CG_EINVAL, "NULL argument");
+  int rc = h->eng->load(src);
+  if (rc == CG_EINVAL) return fail(CG_EINVAL, "snapshot does not match this run");
+  return engine_status(h, rc);
+}
+
+cg_status cg_lbm_set_timing(cg_lbm* h, int mask) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  h->eng->set_timing(mask);
+  return CG_OK;
+}
+
+cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n) {
+  if (!h || !names || !counts || !total_ms || !n) return fail(CG_EINVAL, "NULL argument");
+  int64_t c[cg::K_COUNT];
+  double ms[cg::K_COUNT];
+  int rc = h->eng->kernel_times(c, ms);
+  if (rc != CG_OK) return engine_status(h, rc);
+  const int m = *n < cg::K_COUNT ? *n : cg::K_COUNT;
+  for (int k = 0; k < m; ++k) {
+    std::strncpy(names[k], cg::kKernelNames[k], 31);
+    names[k][31] = 0;
+    counts[k] = c[k];
+    total_ms[k] = ms[k];
+  }
+  *n = m;
+  return CG_OK;
+}
+
+cg_status cg_lbm_reset_timing(cg_lbm* h) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  h->eng->reset_timing();
+  return CG_OK;
+}
+
+}  // extern "C"

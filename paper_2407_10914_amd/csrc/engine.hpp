@@ -1,0 +1,498 @@
+// Per-run device engine: owns the device arrays of one run and enqueues the
+// kernels of the time step, the observables and the state transfers on the
+// run's stream.  Engine<double> and Engine<float> are instantiated in their
+// own translation units (different floating-point contraction flags).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine_base.hpp"
+#include "kernels.hpp"
+
+namespace cg {
+
+#define CG_HIP(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) {                        \
+      err_ = hipGetErrorString(e_);           \
+      return CG_EHIP;                              \
+    }                                              \
+  } while (0)
+
+template <class Real>
+class Engine final : public EngineBase {
+  static constexpr bool kF32 = sizeof(Real) == 4;
+  static constexpr int BS = 256;
+
+ public:
+  ~Engine() override {
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (void* p : owned_) al_->put(p);
+    for (auto& ev : ev_pool_) (void)hipEventDestroy(ev);
+  }
+
+  int init(const HostSetup& S, const StepParams& P, int block, Alloc* al, hipStream_t st,
+           std::string* err) override {
+    (void)block;
+    al_ = al;
+    stream_ = st;
+    P_ = P;
+    dim_ = S.dim;
+    Q_ = S.Q;
+    const size_t Np = (size_t)S.Np, V = (size_t)S.V;
+    const size_t Q = (size_t)S.Q, D = (size_t)S.dim;
+    auto dev = [&](size_t bytes) -> void* {
+      void* p = al_->get(bytes);
+      if (p) owned_.push_back(p);
+      return p;
+    };
+    int* nbr = (int*)dev(sizeof(int) * (Q - 1) * Np);
+    int* vox = (int*)dev(sizeof(int) * Np);
+    unsigned* flags = (unsigned*)dev(sizeof(unsigned) * Np);
+    const size_t nsb = S.sb_vox.size();
+    int* sbv = (int*)dev(sizeof(int) * (nsb ? nsb : 1));
+    unsigned* sbm = (unsigned*)dev(sizeof(unsigned) * (nsb ? nsb : 1));
+    Real* nw = (Real*)dev(sizeof(Real) * 3 * Np);
+    Real* ct = (Real*)dev(sizeof(Real) * Np);
+    Real* stt = (Real*)dev(sizeof(Real) * Np);
+    Real* phi = (Real*)dev(sizeof(Real) * V);
+    Real* ng = (Real*)dev(sizeof(Real) * D * V);
+    Real* cv = (Real*)dev(sizeof(Real) * D * Np);
+    const int nb = (S.N + BS - 1) / BS;
+    obs_part_ = (double*)dev(sizeof(double) * (size_t)kObsN * (nb + 1));
+    obs_out_ = (double*)dev(sizeof(double) * kObsN);
+    if (kF32) {
+      for (int k = 0; k < 2; ++k) {
+        T_[k] = (float*)dev(sizeof(float) * Q * Np);
+        A_[k] = (float*)dev(sizeof(float) * Np);
+        Cc_[k] = (float*)dev(sizeof(float) * D * Np);
+      }
+      pre_r_ = (Real*)dev(sizeof(Real) * Q * Np);
+      pre_x_ = (Real*)dev(sizeof(Real) * Q * Np);
+      state_bytes_ = sizeof(float) * (Q + 1 + D) * Np;
+    } else {
+      for (int k = 0; k < 2; ++k) {
+        fr_[k] = (Real*)dev(sizeof(Real) * Q * Np);
+        fb_[k] = (Real*)dev(sizeof(Real) * Q * Np);
+      }
+      state_bytes_ = sizeof(Real) * 2 * Q * Np;
+    }
+    for (void* p : owned_)
+      if (!p) {
+        *err = "device allocation failed";
+        return CG_ENOMEM;
+      }
+    // upload
+    std::vector<int> voxp(Np, 0);
+    std::copy(S.node_vox.begin(), S.node_vox.end(), voxp.begin());
+    std::vector<Real> nwr(3 * Np), ctr(Np), str(Np);
+    for (size_t i = 0; i < 3 * Np; ++i) nwr[i] = (Real)S.nw[i];
+    for (size_t i = 0; i < Np; ++i) {
+      ctr[i] = (Real)S.cos_t[i];
+      str[i] = (Real)S.sin_t[i];
+    }
+    hipError_t e = hipSuccess;
+    auto up = [&](void* d, const void* h, size_t bytes) {
+      if (e == hipSuccess && bytes) e = hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
+    };
+    up(nbr, S.nbr.data(), sizeof(int) * (Q - 1) * Np);
+    up(vox, voxp.data(), sizeof(int) * Np);
+    up(flags, S.flags.data(), sizeof(unsigned) * Np);
+    up(sbv, S.sb_vox.data(), sizeof(int) * nsb);
+    up(sbm, S.sb_mask.data(), sizeof(unsigned) * nsb);
+    up(nw, nwr.data(), sizeof(Real) * 3 * Np);
+    up(ct, ctr.data(), sizeof(Real) * Np);
+    up(stt, str.data(), sizeof(Real) * Np);
+    if (e == hipSuccess) e = hipMemset(phi, 0, sizeof(Real) * V);
+    if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(Real) * D * V);
+    if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(Real) * D * Np);
+    if (e != hipSuccess) {
+      *err = std::string("upload failed: ") + hipGetErrorString(e);
+      return CG_EHIP;
+    }
+    G_ = Geo<Real>{nbr, vox, flags, sbv, sbm, nw, ct, stt};
+    R_ = Grids<Real>{phi, ng, cv};
+    nsb_ = (int)nsb;
+    dev_bytes_ = al_->total;
+    // rest state, all fluid b
+    std::vector<double> phi0(S.N, -1.0);
+    return set_phase_nodes(phi0.data());
+  }
+
+  int set_phase_nodes(const double* phi_nodes_host) override {
+    double* d = (double*)al_->get(sizeof(double) * P_.N);
+    if (!d) return CG_ENOMEM;
+    hipError_t e = hipMemcpyAsync(d, phi_nodes_host, sizeof(double) * P_.N, hipMemcpyHostToDevice, stream_);
+    Real* r = pre_r();
+    Real* x = pre_x();
+    if (e == hipSuccess) {
+      if (dim_ == 3)
+        launch(-1, k_set_phase<Real, 3>, P_.N, P_, d, r, x);
+      else
+        launch(-1, k_set_phase<Real, 2>, P_.N, P_, d, r, x);
+      e = hipStreamSynchronize(stream_);
+    }
+    al_->put(d);
+    CG_HIP(e);
+    CG_HIP(hipGetLastError());
+    pre_ = true;
+    return CG_OK;
+  }
+
+  int set_state_dense(const double* fr, const double* fb, bool devsrc) override {
+    const size_t bytes = sizeof(double) * (size_t)Q_ * P_.V;
+    const double *a = fr, *b = fb;
+    double *ta = nullptr, *tb = nullptr;
+    if (!devsrc) {
+      ta = (double*)al_->get(bytes);
+      tb = (double*)al_->get(bytes);
+      if (!ta || !tb) {
+        al_->put(ta);
+        al_->put(tb);
+        return CG_ENOMEM;
+      }
+      CG_HIP(hipMemcpyAsync(ta, fr, bytes, hipMemcpyHostToDevice, stream_));
+      CG_HIP(hipMemcpyAsync(tb, fb, bytes, hipMemcpyHostToDevice, stream_));
+      a = ta;
+      b = tb;
+    }
+    if (dim_ == 3)
+      launch(-1, k_import<Real, 3>, P_.N, P_, G_, a, b, pre_r(), pre_x());
+    else
+      launch(-1, k_import<Real, 2>, P_.N, P_, G_, a, b, pre_r(), pre_x());
+    hipError_t e = hipStreamSynchronize(stream_);
+    al_->put(ta);
+    al_->put(tb);
+    CG_HIP(e);
+    CG_HIP(hipGetLastError());
+    pre_ = true;
+    return CG_OK;
+  }
+
+  int step(int64_t n) override {
+    for (int64_t k = 0; k < n; ++k) {
+      if (dim_ == 3)
+        one_step<3>();
+      else
+        one_step<2>();
+      ++t;
+    }
+    CG_HIP(hipGetLastError());
+    return CG_OK;
+  }
+
+  int macro(double* rr, double* rb, double* u, double* kap, double* F, double* C) override {
+    MacroOut mo{rr, rb, nullptr, u, kap, F, C};
+    if (dim_ == 3)
+      run_macro<3>(mo);
+    else
+      run_macro<2>(mo);
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipStreamSynchronize(stream_));
+    return CG_OK;
+  }
+
+  int phi_grid(double* dst) override {
+    if (dim_ == 3) {
+      front<3>(2);
+    } else {
+      front<2>(2);
+    }
+    launch(-1, k_grid_copy<Real>, P_.V, P_.V, (const int*)nullptr, 1, P_.V, (const Real*)R_.phi, dst);
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipStreamSynchronize(stream_));
+    return CG_OK;
+  }
+
+  int n_grid(double* dst) override {
+    if (dim_ == 3)
+      front<3>(4);
+    else
+      front<2>(4);
+    launch(-1, k_grid_copy<Real>, P_.V, P_.V, (const int*)nullptr, dim_, P_.V, (const Real*)R_.n, dst);
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipStreamSynchronize(stream_));
+    return CG_OK;
+  }
+
+  int export_pops(double* fr, double* fb) override {
+    if (dim_ == 3)
+      run_export<3>(fr, fb);
+    else
+      run_export<2>(fr, fb);
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipStreamSynchronize(stream_));
+    return CG_OK;
+  }
+
+  int observe(int axis, int plane, double* out) override {
+    P_.flux_axis = axis;
+    P_.flux_plane = plane;
+    if (dim_ == 3)
+      run_obs<3>();
+    else
+      run_obs<2>();
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipMemcpyAsync(out, obs_out_, sizeof(double) * kObsN, hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    return CG_OK;
+  }
+
+  // snapshot: header (time, pre flag, cur) + the live state buffers
+  size_t snapshot_bytes() const override { return 64 + state_bytes_ + (kF32 ? 0 : 0) + pre_bytes(); }
+  int save(void* dst) override {
+    CG_HIP(hipStreamSynchronize(stream_));
+    char* p = (char*)dst;
+    int64_t hdr[8] = {t, pre_ ? 1 : 0, cur_, (int64_t)state_bytes_, (int64_t)pre_bytes(), 0, 0, 0};
+    std::memcpy(p, hdr, 64);
+    p += 64;
+    for (auto& s : state_segments(cur_)) {
+      CG_HIP(hipMemcpy(p, s.first, s.second, hipMemcpyDeviceToHost));
+      p += s.second;
+    }
+    if (kF32) {
+      const size_t b = pre_bytes() / 2;
+      CG_HIP(hipMemcpy(p, pre_r_, b, hipMemcpyDeviceToHost));
+      CG_HIP(hipMemcpy(p + b, pre_x_, b, hipMemcpyDeviceToHost));
+    }
+    return CG_OK;
+  }
+  int load(const void* src) override {
+    CG_HIP(hipStreamSynchronize(stream_));
+    const char* p = (const char*)src;
+    int64_t hdr[8];
+    std::memcpy(hdr, p, 64);
+    if (hdr[3] != (int64_t)state_bytes_ || hdr[4] != (int64_t)pre_bytes()) return CG_EINVAL;
+    p += 64;
+    t = hdr[0];
+    pre_ = hdr[1] != 0;
+    cur_ = (int)hdr[2];
+    for (auto& s : state_segments(cur_)) {
+      CG_HIP(hipMemcpy(s.first, p, s.second, hipMemcpyHostToDevice));
+      p += s.second;
+    }
+    if (kF32) {
+      const size_t b = pre_bytes() / 2;
+      CG_HIP(hipMemcpy(pre_r_, p, b, hipMemcpyHostToDevice));
+      CG_HIP(hipMemcpy(pre_x_, p + b, b, hipMemcpyHostToDevice));
+    }
+    return CG_OK;
+  }
+
+  void set_timing(int mask) override { timing_ = mask; }
+  int kernel_times(int64_t* counts, double* ms) override {
+    CG_HIP(hipStreamSynchronize(stream_));
+    collect();
+    for (int k = 0; k < K_COUNT; ++k) {
+      counts[k] = tcount_[k];
+      ms[k] = tms_[k];
+    }
+    return CG_OK;
+  }
+  void reset_timing() override {
+    (void)hipStreamSynchronize(stream_);
+    collect();
+    for (int k = 0; k < K_COUNT; ++k) {
+      tcount_[k] = 0;
+      tms_[k] = 0.0;
+    }
+  }
+  size_t state_bytes() const override { return state_bytes_; }
+  size_t device_bytes() const override { return al_ ? al_->total : dev_bytes_; }
+
+ private:
+  StepParams P_{};
+  Geo<Real> G_{};
+  Grids<Real> R_{};
+  Alloc* al_ = nullptr;
+  hipStream_t stream_ = nullptr;
+  int dim_ = 3, Q_ = 19, nsb_ = 0, cur_ = 0;
+  bool pre_ = true;
+  Real* fr_[2] = {nullptr, nullptr};
+  Real* fb_[2] = {nullptr, nullptr};
+  float* T_[2] = {nullptr, nullptr};
+  float* A_[2] = {nullptr, nullptr};
+  float* Cc_[2] = {nullptr, nullptr};
+  Real* pre_r_ = nullptr;
+  Real* pre_x_ = nullptr;
+  double* obs_part_ = nullptr;
+  double* obs_out_ = nullptr;
+  size_t state_bytes_ = 0, dev_bytes_ = 0;
+  std::vector<void*> owned_;
+  // timing
+  int timing_ = 0;
+  std::vector<hipEvent_t> ev_pool_;
+  struct Rec {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs_;
+  int64_t tcount_[K_COUNT] = {0};
+  double tms_[K_COUNT] = {0};
+
+  size_t pre_bytes() const { return kF32 ? sizeof(Real) * 2 * (size_t)Q_ * P_.Np : 0; }
+  // the canonical double state uses the current ping-pong buffers as staging
+  Real* pre_r() { return kF32 ? pre_r_ : fr_[cur_]; }
+  Real* pre_x() { return kF32 ? pre_x_ : fb_[cur_]; }
+
+  std::vector<std::pair<void*, size_t>> state_segments(int c) {
+    const size_t Np = P_.Np, Q = Q_, D = dim_;
+    if (kF32)
+      return {{T_[c], sizeof(float) * Q * Np}, {A_[c], sizeof(float) * Np}, {Cc_[c], sizeof(float) * D * Np}};
+    return {{fr_[c], sizeof(Real) * Q * Np}, {fb_[c], sizeof(Real) * Q * Np}};
+  }
+
+  hipEvent_t get_event() {
+    if (!ev_pool_.empty()) {
+      hipEvent_t e = ev_pool_.back();
+      ev_pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void collect() {
+    for (auto& r : recs_) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        tcount_[r.k] += 1;
+        tms_[r.k] += ms;
+      }
+      ev_pool_.push_back(r.a);
+      ev_pool_.push_back(r.b);
+    }
+    recs_.clear();
+  }
+
+  template <class K, class... Args>
+  void launch(int kid, K kern, int nthreads, Args... args) {
+    if (nthreads <= 0) return;
+    const int nb = (nthreads + BS - 1) / BS;
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool tm = kid >= 0 && (timing_ & (1 << kid));
+    if (tm) {
+      a = get_event();
+      b = get_event();
+      (void)hipEventRecord(a, stream_);
+    }
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(BS), 0, stream_, args...);
+    if (tm) {
+      (void)hipEventRecord(b, stream_);
+      recs_.push_back({kid, a, b});
+      if (recs_.size() > 4096) {
+        (void)hipStreamSynchronize(stream_);
+        collect();
+      }
+    }
+  }
+
+  template <int D>
+  auto in_post() const {
+    if constexpr (kF32)
+      return InCompact<D>{T_[cur_], A_[cur_], Cc_[cur_], P_.Np, (float)P_.rho0};
+    else
+      return InCanon<Real, D>{fr_[cur_], fb_[cur_], P_.Np};
+  }
+  template <int D>
+  auto in_pre() const {
+    if constexpr (kF32)
+      return InPre<Real, D>{pre_r_, pre_x_, P_.Np};
+    else
+      return InPre<Real, D>{fr_[cur_], fb_[cur_], P_.Np};
+  }
+  template <int D>
+  auto out_next() const {
+    const int nx = cur_ ^ 1;
+    if constexpr (kF32)
+      return OutCompact<D>{T_[nx], A_[nx], Cc_[nx], P_.Np};
+    else
+      return OutCanon<Real, D>{fr_[nx], fb_[nx], P_.Np};
+  }
+
+  // phase field (and optionally the normals): stages 1..upto of the step
+  template <int D, class In>
+  void front_with(const In& in, int upto) {
+    launch(K_PHASE, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
+    if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
+    if (upto >= 3) launch(K_NORMAL, k_normal<Real, D>, P_.N, P_, G_, R_);
+    if (upto >= 4 && nsb_) launch(K_SB_N, k_sb_n<Real, D>, nsb_, P_, G_, R_);
+  }
+  template <int D>
+  void front(int upto) {
+    if (pre_)
+      front_with<D>(in_pre<D>(), upto);
+    else
+      front_with<D>(in_post<D>(), upto);
+  }
+
+  template <int D>
+  void one_step() {
+    auto out = out_next<D>();
+    if (pre_) {
+      auto in = in_pre<D>();
+      front_with<D>(in, 4);
+      launch(K_MAIN, k_main<Real, D, BS, MODE_STEP, decltype(in), decltype(out)>, P_.N, P_, G_, R_, in, out,
+             MacroOut{}, ObsOut{});
+    } else {
+      auto in = in_post<D>();
+      front_with<D>(in, 4);
+      launch(K_MAIN, k_main<Real, D, BS, MODE_STEP, decltype(in), decltype(out)>, P_.N, P_, G_, R_, in, out,
+             MacroOut{}, ObsOut{});
+    }
+    cur_ ^= 1;
+    pre_ = false;
+  }
+
+  template <int D, class In>
+  void macro_with(const In& in, MacroOut mo) {
+    front_with<D>(in, 4);
+    auto out = out_next<D>();
+    launch(-1, k_main<Real, D, BS, MODE_MACRO, In, decltype(out)>, P_.N, P_, G_, R_, in, out, mo, ObsOut{});
+  }
+  template <int D>
+  void run_macro(MacroOut mo) {
+    if (pre_)
+      macro_with<D>(in_pre<D>(), mo);
+    else
+      macro_with<D>(in_post<D>(), mo);
+  }
+
+  template <int D, class In>
+  void obs_with(const In& in) {
+    front_with<D>(in, 4);
+    auto out = out_next<D>();
+    const int nb = (P_.N + BS - 1) / BS;
+    launch(-1, k_main<Real, D, BS, MODE_OBS, In, decltype(out)>, P_.N, P_, G_, R_, in, out, MacroOut{},
+           ObsOut{obs_part_});
+    hipLaunchKernelGGL(k_obs_final<Real>, dim3(1), dim3(64), 0, stream_, (const double*)obs_part_, nb, obs_out_);
+  }
+  template <int D>
+  void run_obs() {
+    if (pre_)
+      obs_with<D>(in_pre<D>());
+    else
+      obs_with<D>(in_post<D>());
+  }
+
+  template <int D, class In>
+  void export_with(const In& in, double* fr, double* fb) {
+    launch(-1, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
+    launch(-1, k_export<Real, D, In>, P_.N, P_, G_, R_, in, fr, fb);
+  }
+  template <int D>
+  void run_export(double* fr, double* fb) {
+    if (pre_)
+      export_with<D>(in_pre<D>(), fr, fb);
+    else
+      export_with<D>(in_post<D>(), fr, fb);
+  }
+};
+
+}  // namespace cg

@@ -1,0 +1,71 @@
+// Precision-independent interface of the per-run device engine, so that the
+// C ABI layer does not instantiate any kernel itself.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "setup.hpp"
+#include "step.hpp"
+
+namespace cg {
+
+struct Alloc {
+  cg_alloc_fn fn = nullptr;
+  cg_free_fn fr = nullptr;
+  void* ctx = nullptr;
+  size_t total = 0;
+  void* get(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (fn) {
+      p = fn(bytes, ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) total += bytes;
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    if (fr)
+      fr(p, ctx);
+    else
+      (void)hipFree(p);
+  }
+};
+
+enum { K_PHASE = 0, K_SB_PHI, K_NORMAL, K_SB_N, K_MAIN, K_COUNT };
+static const char* const kKernelNames[K_COUNT] = {"k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_main"};
+
+struct EngineBase {
+  virtual ~EngineBase() = default;
+  virtual int init(const HostSetup& S, const StepParams& P, int block, Alloc* al, hipStream_t st,
+                   std::string* err) = 0;
+  virtual int set_phase_nodes(const double* phi_nodes_host) = 0;
+  virtual int set_state_dense(const double* fr, const double* fb, bool dev) = 0;
+  virtual int step(int64_t n) = 0;
+  virtual int macro(double* rr, double* rb, double* u, double* kap, double* F, double* C) = 0;
+  virtual int phi_grid(double* dst) = 0;
+  virtual int n_grid(double* dst) = 0;
+  virtual int export_pops(double* fr, double* fb) = 0;
+  virtual int observe(int axis, int plane, double* out) = 0;
+  virtual size_t snapshot_bytes() const = 0;
+  virtual int save(void* dst) = 0;
+  virtual int load(const void* src) = 0;
+  virtual void set_timing(int mask) = 0;
+  virtual int kernel_times(int64_t* counts, double* ms) = 0;
+  virtual void reset_timing() = 0;
+  virtual size_t state_bytes() const = 0;
+  virtual size_t device_bytes() const = 0;
+  int64_t t = 0;
+  std::string err_;
+};
+
+EngineBase* make_engine_f64();
+EngineBase* make_engine_f32();
+
+}  // namespace cg

@@ -1,0 +1,35 @@
+// Once-per-run host setup (FP64): voxel classes, boundary sets along lattice
+// links, the smoothed image and wall normal of Eqs. (25)-(26), the contact
+// angle at each fluid boundary point, the sparse fluid-node index and the pull
+// table.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cg_lbm.h"
+
+namespace cg {
+
+struct HostSetup {
+  int dim = 3, Q = 19, nx = 0, ny = 0, nz = 0, V = 0;
+  int per[3] = {0, 0, 0};
+  int bc = 0;
+  int N = 0;   // fluid nodes
+  int Np = 0;  // padded stride
+  int n_fb = 0, n_in = 0, n_out = 0;
+  std::vector<int> node_vox;    // [N]
+  std::vector<int> nbr;         // [(Q-1) * Np]
+  std::vector<unsigned> flags;  // [Np]
+  std::vector<int> sb_vox;      // [nsb]
+  std::vector<unsigned> sb_mask;
+  std::vector<double> nw;       // [3 * Np]
+  std::vector<double> cos_t, sin_t;  // [Np]
+  std::vector<double> g3;       // smoothed image [V] (kept for diagnostics)
+};
+
+// Returns CG_OK or an error with *err set.
+int build_setup(const cg_geometry& g, const cg_wetting& w, const cg_bc& bc, HostSetup* out, std::string* err);
+
+}  // namespace cg

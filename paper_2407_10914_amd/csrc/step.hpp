@@ -1,0 +1,597 @@
+// Device code of one colour-gradient time step (arXiv:2407.10914, Sec. II).
+//
+// One thread per fluid node.  Per step the kernels run in the order the
+// method needs (the phase field of all nodes before any gradient, all normals
+// before any curvature):
+//   k_phase   densities and phase field, Eqs. (7)-(9), inlet phi (Sec. II.D.1)
+//             and outlet phi (Eq. 39), written to a dense voxel grid;
+//   k_sb_phi  phase field extrapolated to the solid boundary points, Eq. (34);
+//   k_normal  colour gradient, Eq. (6), unit normal, Eq. (27), wetting
+//             Scheme-I / Scheme-II at the fluid boundary points, Eqs. (28)-(33);
+//   k_sb_n    normal extrapolated to the solid boundary points, Eq. (35);
+//   k_main    pull streaming with halfway bounce-back, Zou-He faces
+//             (Appendix B), curvature, Eq. (12), force, Eqs. (5) and (36),
+//             velocity, Eq. (22), rates, Eqs. (13)-(16), BGK/MRT collision,
+//             Eqs. (2)-(4) and (A.3)-(A.5), recolouring, Eqs. (20)-(21), store.
+//
+// Two state layouts:
+//   double: canonical post-collision populations f^r', f^b' ([Q][Np] each);
+//           every operation follows the order of the reference definition
+//           (sums over i ascending, no fused multiply-add: the translation
+//           unit is built with -ffp-contract=off).
+//   float:  compact post-collision state: g''_i = f^t''_i - w_i rho0 ([Q][Np]),
+//           a = rho^r/rho ([Np]) and c = beta rho^r rho^b / rho * n ([D][Np]).
+//           The recoloured red population that a pull reads is rebuilt as
+//           f^r_i = a (w_i rho0 + g''_i) + w_i c.e_i, which is Eq. (20); the
+//           total is carried as a deviation from rest so that the momentum
+//           is not lost to single-precision rounding of O(1) values.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace cg {
+
+enum : unsigned {
+  FL_FACE = 1u,   // on a domain face: stencils need wrap / clamp
+  FL_WET = 2u,    // fluid boundary point with a usable wall normal
+  FL_IN = 4u,     // Zou-He inlet node (z = 0)
+  FL_OUT = 8u,    // Zou-He outlet node (z = nz-1)
+  FL_S1POS = 16u  // Scheme-I secant start uses s = +1
+};
+
+// number of observable accumulators (see k_main, MODE_OBS)
+constexpr int kObsN = 15;
+
+// Pull-table codes (entries >= 0 are source node indices).
+constexpr int kBounce = -1;
+constexpr int kOpen = -2;
+
+struct StepParams {
+  int nx, ny, nz;
+  int N;     // fluid nodes
+  int Np;    // stride of per-node arrays
+  int nsb;   // solid boundary points
+  int V;     // voxels
+  int per[3];
+  int bc;    // 0 none, 1 Zou-He z faces
+  int scheme;
+  int collision;  // 0 BGK, 1 MRT
+  double half_sigma;  // 0.5 * sigma
+  double beta, rho0;
+  double nu_r, nu_b;  // (tau - 1/2)/3
+  double rg[3];       // rho0 * g, force density of Eq. (36)
+  double rin_r, rin_b;  // rho_in * zeta^r, rho_in * zeta^b
+  double rho_in, rho_out, phi_in;
+  double eps_c, eps_f, eps_v;
+  int flux_axis, flux_plane;
+};
+
+template <class Real>
+struct Geo {
+  const int* nbr;          // [Q-1][Np]: source of direction i (i >= 1) or a code
+  const int* vox;          // [Np] voxel index
+  const unsigned* flags;   // [Np]
+  const int* sb_vox;       // [nsb]
+  const unsigned* sb_mask; // [nsb] bit i: the link s + e_i ends on a fluid voxel in the domain
+  const Real* nw;          // [3][Np] wall normal (unit)
+  const Real* cos_t;       // [Np]
+  const Real* sin_t;       // [Np]
+};
+
+template <class Real>
+struct Grids {
+  Real* phi;   // [V]
+  Real* n;     // [D][V]
+  Real* c;     // [D][Np] colour gradient after wetting
+};
+
+// ------------------------------------------------------------------- helpers
+
+// Block index -> logical tile, so that each of the 8 XCDs (blocks are dealt
+// round-robin) works on one contiguous range of nodes and keeps its stencil
+// neighbours in its own L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ int node_id() {
+  return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
+// Neighbour voxel of v along velocity (ex, ey, ez) for the gradient stencils:
+// periodic axes wrap, other axes clamp (zero-gradient ghosts beyond the open
+// faces; fluid nodes never reach past a wall face).
+__device__ __forceinline__ int nb_slow(const StepParams& P, int v, int ex, int ey, int ez) {
+  const int nxy = P.nx * P.ny;
+  int z = v / nxy;
+  int r = v - z * nxy;
+  int y = r / P.nx;
+  int x = r - y * P.nx;
+  x += ex;
+  y += ey;
+  z += ez;
+  if (x < 0) x = P.per[0] ? x + P.nx : 0;
+  if (x >= P.nx) x = P.per[0] ? x - P.nx : P.nx - 1;
+  if (y < 0) y = P.per[1] ? y + P.ny : 0;
+  if (y >= P.ny) y = P.per[1] ? y - P.ny : P.ny - 1;
+  if (z < 0) z = P.per[2] ? z + P.nz : 0;
+  if (z >= P.nz) z = P.per[2] ? z - P.nz : P.nz - 1;
+  return x + P.nx * (y + P.ny * z);
+}
+
+template <int D, int i>
+__device__ __forceinline__ int nb_vox(const StepParams& P, int v, bool face) {
+  constexpr int ex = Lat<D>::e(i, 0), ey = Lat<D>::e(i, 1), ez = Lat<D>::e(i, 2);
+  if (face) return nb_slow(P, v, ex, ey, ez);
+  return v + ex + P.nx * (ey + P.ny * ez);
+}
+
+template <class Real, int D>
+__device__ __forceinline__ Real dotv(const Real* a, const Real* b) {
+  Real s = a[0] * b[0];
+  s = s + a[1] * b[1];
+  if constexpr (D == 3) s = s + a[2] * b[2];
+  return s;
+}
+
+// ------------------------------------------------------------ state layouts
+
+// Canonical post-collision populations (double path).
+template <class Real, int D>
+struct InCanon {
+  static constexpr bool kPull = true;
+  const Real* fr;
+  const Real* fb;
+  int Np;
+  template <int i, class CT>
+  __device__ __forceinline__ void get(int s, CT& r, CT& x) const {
+    r = (CT)fr[i * Np + s];
+    x = (CT)fb[i * Np + s];
+  }
+};
+
+// Compact post-collision state (float path); x = g = f^t - w rho0.
+template <int D>
+struct InCompact {
+  static constexpr bool kPull = true;
+  const float* T;
+  const float* A;
+  const float* Cc;
+  int Np;
+  float rho0;
+  template <int i, class CT>
+  __device__ __forceinline__ void get(int s, CT& r, CT& x) const {
+    constexpr double w = Lat<D>::w(i);
+    const CT t = (CT)T[i * Np + s];
+    const CT a = (CT)A[s];
+    CT r0 = a * ((CT)w * (CT)rho0 + t);
+    if constexpr (i != 0) {
+      CT ce = CT(0);
+      unroll<D>([&](auto A_) {
+        constexpr int d = A_;
+        constexpr int e = Lat<D>::e(i, d);
+        if constexpr (e == 1) ce = ce + (CT)Cc[d * Np + s];
+        if constexpr (e == -1) ce = ce - (CT)Cc[d * Np + s];
+      });
+      r0 = r0 + (CT)w * ce;
+    }
+    r = r0;
+    x = t;
+  }
+};
+
+// Pre-collision populations stored at their own node (first step after the
+// state was set from the host).
+template <class Real, int D>
+struct InPre {
+  static constexpr bool kPull = false;
+  const Real* r_;
+  const Real* x_;
+  int Np;
+  template <int i, class CT>
+  __device__ __forceinline__ void get(int s, CT& r, CT& x) const {
+    r = (CT)r_[i * Np + s];
+    x = (CT)x_[i * Np + s];
+  }
+};
+
+template <class Real, int D>
+struct OutCanon {
+  Real* fr;
+  Real* fb;
+  int Np;
+};
+
+template <int D>
+struct OutCompact {
+  float* T;
+  float* A;
+  float* Cc;
+  int Np;
+};
+
+// Gather the pre-collision populations of node n (pull streaming with halfway
+// bounce-back: f_i(x) = f'_i(x - e_i) from a fluid source, f'_opp(i)(x) when
+// the source is solid; open-face unknowns are left 0 for the Zou-He step).
+template <int D, class In, class CT>
+__device__ __forceinline__ void load_node(const In& in, const int* nbr, int Np, int n, CT* fr, CT* fx) {
+  constexpr int Q = Lat<D>::Q;
+  int src[Q];
+  if constexpr (In::kPull) {
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      src[i] = nbr[(i - 1) * Np + n];
+    });
+  }
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    if constexpr (In::kPull && i > 0) {
+      const int s = src[i];
+      if (s >= 0) {
+        in.template get<i>(s, fr[i], fx[i]);
+      } else if (s == kBounce) {
+        in.template get<opp<D>(i)>(n, fr[i], fx[i]);
+      } else {
+        fr[i] = CT(0);
+        fx[i] = CT(0);
+      }
+    } else {
+      in.template get<i>(n, fr[i], fx[i]);
+    }
+  });
+}
+
+// -------------------------------------------------------------- Zou-He faces
+
+// Inlet, one colour (or the total deviation), Eqs. (B.1)-(B.8).
+template <class CT>
+__device__ __forceinline__ void zh_in(CT* f, CT rho_s) {
+  CT S = f[0] + f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[9] + f[10];
+  CT T = f[6] + f[13] + f[14] + f[17] + f[18];
+  CT j = rho_s - (S + CT(2) * T);
+  CT Nx = CT(0.5) * ((f[1] + f[7] + f[9]) - (f[2] + f[8] + f[10]));
+  CT Ny = CT(0.5) * ((f[3] + f[7] + f[8]) - (f[4] + f[9] + f[10]));
+  f[5] = f[6] + j / CT(3);
+  f[11] = f[14] + j / CT(6) - Nx;
+  f[12] = f[13] + j / CT(6) + Nx;
+  f[15] = f[18] + j / CT(6) - Ny;
+  f[16] = f[17] + j / CT(6) + Ny;
+}
+
+// Outlet unknowns for one colour given jc = jt * chi^s, Eqs. (B.10)-(B.18).
+template <class CT>
+__device__ __forceinline__ void zh_out_color(CT* f, CT jc) {
+  CT Nx = CT(0.5) * ((f[1] + f[7] + f[9]) - (f[2] + f[8] + f[10]));
+  CT Ny = CT(0.5) * ((f[3] + f[7] + f[8]) - (f[4] + f[9] + f[10]));
+  f[6] = f[5] - jc / CT(3);
+  f[13] = f[12] - jc / CT(6) - Nx;
+  f[14] = f[11] - jc / CT(6) + Nx;
+  f[17] = f[16] - jc / CT(6) - Ny;
+  f[18] = f[15] - jc / CT(6) + Ny;
+}
+
+// Apply the faces to node populations.  Canonical layout: x = f^b, per-colour
+// inlet and chi-weighted outlet exactly as written.  Deviation layout
+// (x = f^t - w rho0): the red colour as written, the total with the deviation
+// densities (the weights of the known directions sum to 1 for both faces).
+template <bool kDev, class CT>
+__device__ __forceinline__ void zou_he(const StepParams& P, unsigned fl, CT phi_up, CT* fr, CT* fx) {
+  if (fl & FL_IN) {
+    zh_in(fr, (CT)P.rin_r);
+    if constexpr (kDev)
+      zh_in(fx, (CT)(P.rho_in - P.rho0));
+    else
+      zh_in(fx, (CT)P.rin_b);
+  } else if (fl & FL_OUT) {
+    CT jt;
+    if constexpr (kDev) {
+      CT S = fx[0] + fx[1] + fx[2] + fx[3] + fx[4] + fx[7] + fx[8] + fx[9] + fx[10];
+      CT T = fx[5] + fx[11] + fx[12] + fx[15] + fx[16];
+      jt = -(CT)(P.rho_out - P.rho0) + (S + CT(2) * T);
+      zh_out_color(fr, jt * (CT(0.5) * (CT(1) + phi_up)));
+      zh_out_color(fx, jt);
+    } else {
+      CT ft[19];
+#pragma unroll
+      for (int i = 0; i < 19; ++i) ft[i] = fr[i] + fx[i];
+      CT S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
+      CT T = ft[5] + ft[11] + ft[12] + ft[15] + ft[16];
+      jt = -(CT)P.rho_out + (S + CT(2) * T);
+      CT chr = CT(0.5) * (CT(1) + phi_up);
+      CT chb = CT(0.5) * (CT(1) - phi_up);
+      zh_out_color(fr, jt * chr);
+      zh_out_color(fx, jt * chb);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ moments
+
+// Densities of the loaded node: rr = sum f^r, rb, rho (Eqs. 8-9), drho (the
+// density handed to the equilibrium: rho itself, or the deviation sum of g
+// that never rounds through rho), and the total populations ft used by the
+// collision (canonical: f^r + f^b; deviation: g as loaded).
+// Deviation layout: rho (used for phi, rho^b and the recolouring fractions)
+// is the sum of the rebuilt totals w_i rho0 + g_i with the same single-
+// precision weights the pull uses to rebuild f^r.  Those weights do not sum
+// to exactly 1 (the excess is about 1.5e-8), and dividing rho^r by rho0 +
+// sum g instead would grow the red mass by that excess every step.
+template <int D, bool kDev, class CT>
+__device__ __forceinline__ void node_moments(const CT* fr, CT* fx, CT rho0, CT& rr, CT& rb, CT& rho, CT& drho) {
+  constexpr int Q = Lat<D>::Q;
+  CT a = fr[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) a = a + fr[i];
+  CT b = fx[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) b = b + fx[i];
+  rr = a;
+  if constexpr (kDev) {
+    drho = b;
+    CT t = (CT)Lat<D>::w(0) * rho0 + fx[0];
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      t = t + ((CT)Lat<D>::w(i) * rho0 + fx[i]);
+    });
+    rho = t;
+    rb = t - a;
+  } else {
+    rb = b;
+    rho = a + b;
+    drho = rho;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fx[i] = fr[i] + fx[i];  // fx becomes f^t
+  }
+}
+
+// ------------------------------------------------------------------ wetting
+
+// Scheme-I, Eqs. (28)-(31): secant on f(v) = v.n_w - |v| cos(theta) along the
+// line through v0 = n_c and v1 = n_c - (n_c + s n_w)/2, three secant steps,
+// guards on |f|, on the secant denominator, on |v| and on n_c || n_w.
+template <class CT, int D>
+__device__ __forceinline__ void scheme1(CT* n, const CT* nw, CT cos_t, CT sgn, CT eps_f, CT eps_v) {
+  CT cr;
+  if constexpr (D == 3) {
+    CT c0 = n[1] * nw[2] - n[2] * nw[1];
+    CT c1 = n[2] * nw[0] - n[0] * nw[2];
+    CT c2 = n[0] * nw[1] - n[1] * nw[0];
+    cr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+  } else {
+    cr = fabs(n[0] * nw[1] - n[1] * nw[0]);
+  }
+  if (cr <= eps_v) return;
+  CT v0[3], v1[3];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    v0[c] = n[c];
+    v1[c] = n[c] - CT(0.5) * (n[c] + sgn * nw[c]);
+  }
+  CT f0 = dotv<CT, D>(v0, nw) - sqrt(dotv<CT, D>(v0, v0)) * cos_t;
+  CT f1 = dotv<CT, D>(v1, nw) - sqrt(dotv<CT, D>(v1, v1)) * cos_t;
+  for (int it = 2; it <= 4; ++it) {
+    if (fabs(f1) <= eps_f || fabs(f1 - f0) <= eps_f) break;
+    CT v2[3];
+#pragma unroll
+    for (int c = 0; c < D; ++c) v2[c] = (v0[c] * f1 - v1[c] * f0) / (f1 - f0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      v0[c] = v1[c];
+      v1[c] = v2[c];
+    }
+    f0 = f1;
+    if (it < 4) f1 = dotv<CT, D>(v1, nw) - sqrt(dotv<CT, D>(v1, v1)) * cos_t;
+  }
+  CT nv = sqrt(dotv<CT, D>(v1, v1));
+  if (nv <= eps_v) return;
+#pragma unroll
+  for (int c = 0; c < D; ++c) n[c] = v1[c] / nv;
+}
+
+// Scheme-II, Eqs. (32)-(33), with cos(theta') = n_w.n_c and
+// sin(theta') = |n_c - (n_w.n_c) n_w|; the candidate nearer to n_c is kept.
+template <class CT, int D>
+__device__ __forceinline__ void scheme2(CT* n, const CT* nw, CT cos_t, CT sin_t, CT eps_v) {
+  CT ctp = dotv<CT, D>(nw, n);
+  CT t[3];
+#pragma unroll
+  for (int c = 0; c < D; ++c) t[c] = n[c] - ctp * nw[c];
+  CT stp = sqrt(dotv<CT, D>(t, t));
+  if (stp <= eps_v) return;
+  CT np[3], nm[3];
+  {
+    CT s = sin_t;
+    CT A = cos_t - s * ctp / stp;
+    CT B = s / stp;
+#pragma unroll
+    for (int c = 0; c < D; ++c) np[c] = A * nw[c] + B * n[c];
+  }
+  {
+    CT s = -sin_t;
+    CT A = cos_t - s * ctp / stp;
+    CT B = s / stp;
+#pragma unroll
+    for (int c = 0; c < D; ++c) nm[c] = A * nw[c] + B * n[c];
+  }
+  CT dp = (np[0] - n[0]) * (np[0] - n[0]);
+  CT dm = (nm[0] - n[0]) * (nm[0] - n[0]);
+#pragma unroll
+  for (int c = 1; c < D; ++c) {
+    dp = dp + (np[c] - n[c]) * (np[c] - n[c]);
+    dm = dm + (nm[c] - n[c]) * (nm[c] - n[c]);
+  }
+  if (dp <= dm) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) n[c] = np[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < D; ++c) n[c] = nm[c];
+  }
+}
+
+// ---------------------------------------------------------------- collision
+
+// Equilibrium (deviation from w_i rho0 when kDev) of the incompressible
+// model: h_i = w_i [drho + rho0 (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)], with
+// drho = rho (canonical) or rho - rho0 (deviation).
+template <int D, int i, class CT>
+__device__ __forceinline__ CT eq_i(CT drho, CT rho0, const CT* u, CT usq) {
+  constexpr double w = Lat<D>::w(i);
+  CT eu = CT(0);
+  bool first = true;
+  unroll<D>([&](auto A_) {
+    constexpr int a = A_;
+    constexpr int e = Lat<D>::e(i, a);
+    if constexpr (e != 0) {
+      const CT t = e == 1 ? u[a] : -u[a];
+      eu = first ? t : eu + t;
+      first = false;
+    }
+  });
+  return (CT)w * (drho + rho0 * (CT(3) * eu + CT(4.5) * eu * eu - CT(1.5) * usq));
+}
+
+// Guo forcing population: w_i [3 (e_i - u).F + 9 (e_i.u)(e_i.F)].
+template <int D, int i, class CT>
+__device__ __forceinline__ CT guo_i(const CT* u, const CT* F) {
+  constexpr double w = Lat<D>::w(i);
+  CT emuF = ((CT)Lat<D>::e(i, 0) - u[0]) * F[0];
+  emuF = emuF + ((CT)Lat<D>::e(i, 1) - u[1]) * F[1];
+  if constexpr (D == 3) emuF = emuF + ((CT)Lat<D>::e(i, 2) - u[2]) * F[2];
+  CT eu = CT(0), eF = CT(0);
+  bool first = true;
+  unroll<D>([&](auto A_) {
+    constexpr int a = A_;
+    constexpr int e = Lat<D>::e(i, a);
+    if constexpr (e != 0) {
+      const CT tu = e == 1 ? u[a] : -u[a];
+      const CT tF = e == 1 ? F[a] : -F[a];
+      eu = first ? tu : eu + tu;
+      eF = first ? tF : eF + tF;
+      first = false;
+    }
+  });
+  return (CT)w * (CT(3) * emuF + CT(9) * eu * eF);
+}
+
+// sum_j M_kj v_j over the non-zero entries in ascending j
+template <int k, class CT>
+__device__ __forceinline__ CT mrow(const CT* v) {
+  CT s = CT(0);
+  bool first = true;
+  unroll<19>([&](auto J) {
+    constexpr int j = J;
+    constexpr int m = Mkj(k, j);
+    if constexpr (m != 0) {
+      CT t;
+      if constexpr (m == 1)
+        t = v[j];
+      else if constexpr (m == -1)
+        t = -v[j];
+      else
+        t = (CT)m * v[j];
+      s = first ? t : s + t;
+      first = false;
+    }
+  });
+  return s;
+}
+
+// MRT collision on the total distribution:
+// f'' = f - M^-1 [ S (m - m^eq) - (I - S/2) M Fbar ].
+// kExact evaluates m and m^eq separately (reference order); otherwise
+// M (f - f^eq) is formed in one product.
+template <bool kExact, class CT>
+__device__ __forceinline__ void collide_mrt(CT* ft, CT drho, CT rho0, const CT* u, const CT* F, CT s_nu, CT s_q) {
+  constexpr int D = 3;
+  CT usq = u[0] * u[0];
+  usq = usq + u[1] * u[1];
+  usq = usq + u[2] * u[2];
+  CT fe[19], fb[19];
+  unroll<19>([&](auto I) {
+    constexpr int i = I;
+    fe[i] = eq_i<D, i>(drho, rho0, u, usq);
+    fb[i] = guo_i<D, i>(u, F);
+  });
+  CT corr[19];
+  if constexpr (kExact) {
+    unroll<19>([&](auto K) {
+      constexpr int k = K;
+      constexpr int rc = rate_class(k);
+      const CT mm = mrow<k>(ft);
+      const CT me = mrow<k>(fe);
+      const CT mf = mrow<k>(fb);
+      if constexpr (rc == 0) {
+        corr[k] = -mf;
+      } else {
+        const CT S = rc == 1 ? s_nu : s_q;
+        const CT sf = (CT(1) - CT(0.5) * S) * mf;
+        corr[k] = S * (mm - me) - sf;
+      }
+    });
+  } else {
+    CT d[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = ft[i] - fe[i];
+    const CT hnu = CT(1) - CT(0.5) * s_nu, hq = CT(1) - CT(0.5) * s_q;
+    unroll<19>([&](auto K) {
+      constexpr int k = K;
+      constexpr int rc = rate_class(k);
+      const CT mf = mrow<k>(fb);
+      if constexpr (rc == 0) {
+        corr[k] = -mf;
+      } else {
+        const CT md = mrow<k>(d);
+        corr[k] = rc == 1 ? (s_nu * md - hnu * mf) : (s_q * md - hq * mf);
+      }
+    });
+  }
+  unroll<19>([&](auto I) {
+    constexpr int i = I;
+    CT s = CT(0);
+    bool first = true;
+    unroll<19>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (Mkj(k, i) != 0) {
+        const CT t = (CT)Minv(i, k) * corr[k];
+        s = first ? t : s + t;
+        first = false;
+      }
+    });
+    ft[i] = ft[i] - s;
+  });
+}
+
+// Single-relaxation-time collision with Guo forcing:
+// f'' = f - S_nu (f - f^eq) + (1 - S_nu/2) Fbar.
+template <int D, class CT>
+__device__ __forceinline__ void collide_bgk(CT* ft, CT drho, CT rho0, const CT* u, const CT* F, CT s_nu) {
+  CT usq = u[0] * u[0];
+  usq = usq + u[1] * u[1];
+  if constexpr (D == 3) usq = usq + u[2] * u[2];
+  const CT h = CT(1) - CT(0.5) * s_nu;
+  unroll<Lat<D>::Q>([&](auto I) {
+    constexpr int i = I;
+    const CT fe = eq_i<D, i>(drho, rho0, u, usq);
+    const CT fb = guo_i<D, i>(u, F);
+    ft[i] = ft[i] - s_nu * (ft[i] - fe) + h * fb;
+  });
+}
+
+// Rates of Eqs. (13)-(16) from the local phase field.
+template <class CT>
+__device__ __forceinline__ void rates(const StepParams& P, CT phi, CT& s_nu, CT& s_q) {
+  const CT nr = (CT)P.nu_r, nb = (CT)P.nu_b;
+  CT inv_nu = (CT(1) + phi) / (CT(2) * nr) + (CT(1) - phi) / (CT(2) * nb);
+  CT nu = CT(1) / inv_nu;
+  s_nu = CT(1) / (CT(3) * nu + CT(0.5));
+  s_q = (CT(8) * (CT(2) - s_nu)) / (CT(8) - s_nu);
+}
+
+}  // namespace cg

@@ -1,0 +1,199 @@
+"""Python front end of one run: a thin wrapper over the C ABI (lib.py)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import lib as L
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator on the current stream."""
+
+    def __init__(self, device=0):
+        torch = _torch()
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self._live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:  # out of memory: the library reports CG_ENOMEM
+                return None
+
+        def _free(ptr, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
+
+        self.alloc_fn = L.ALLOC_FN(_alloc)
+        self.free_fn = L.FREE_FN(_free)
+
+
+class Sim:
+    """One colour-gradient LBM run on the GPU.
+
+    Arrays are (nz, ny, nx) numpy arrays (x fastest); populations (Q, nz, ny, nx).
+    """
+
+    def __init__(self, solid, *, dim, periodic, tau_r=1.0, tau_b=1.0, sigma=0.0, beta=0.7, scheme=0,
+                 theta_deg=90.0, theta_field=None, s1_line=0, bc=0, rho_in=1.0, rho_out=1.0, zeta_r=0.0,
+                 g=(0.0, 0.0, 0.0), precision="f32", collision=None, rho0=1.0, eps_c=None, eps_f=None,
+                 eps_v=None, device=0, torch_alloc=True):
+        lib = L.load()
+        solid = np.ascontiguousarray(solid, dtype=np.uint8)
+        if solid.ndim == 2:
+            solid = solid[None]
+        self.shape = solid.shape
+        nz, ny, nx = self.shape
+        self._solid = solid
+        geo = L.Geometry(dim, nx, ny, nz, solid.ctypes.data_as(C.c_void_p), (C.c_uint8 * 3)(*periodic))
+        self._tf = None
+        if theta_field is not None:
+            self._tf = np.ascontiguousarray(theta_field, dtype=np.float64).reshape(-1)
+        wet = L.Wetting(int(scheme), float(theta_deg),
+                        None if self._tf is None else self._tf.ctypes.data_as(C.c_void_p), int(s1_line))
+        bcs = L.BC(int(bc), float(rho_in), float(rho_out), float(zeta_r), (C.c_double * 3)(*[float(x) for x in g]))
+        prec = L.CG_FP64 if precision in ("f64", "fp64", "double", L.CG_FP64) else L.CG_FP32
+        opt = L.Options()
+        lib.cg_options_default(C.byref(opt), prec)
+        if collision is None:
+            opt.collision = L.CG_MRT if dim == 3 else L.CG_BGK
+        else:
+            opt.collision = L.CG_MRT if collision in ("mrt", L.CG_MRT) else L.CG_BGK
+        opt.rho0 = rho0
+        for k, v in (("eps_c", eps_c), ("eps_f", eps_f), ("eps_v", eps_v)):
+            if v is not None:
+                setattr(opt, k, v)
+        opt.device = device
+        self._alloc = None
+        if torch_alloc:
+            self._alloc = TorchAllocator(device)
+            opt.stream = self._alloc.stream.cuda_stream
+            opt.alloc = self._alloc.alloc_fn
+            opt.free = self._alloc.free_fn
+        self.precision = "f64" if prec == L.CG_FP64 else "f32"
+        self.dim = dim
+        h = C.c_void_p()
+        L.check(lib.cg_lbm_create(C.byref(geo), tau_r, tau_b, sigma, beta, C.byref(wet), C.byref(bcs),
+                                  C.byref(opt), C.byref(h)))
+        self._h = h
+        inf = self.info()
+        self.q = inf["q"]
+
+    # ------------------------------------------------------------------ admin
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            L.load().cg_lbm_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = L.Info()
+        L.check(L.load().cg_lbm_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    @property
+    def time(self):
+        return L.load().cg_lbm_time(self._h)
+
+    # ------------------------------------------------------------------ state
+    def set_phase(self, phi0):
+        a = np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)
+        assert a.size == self._solid.size
+        L.check(L.load().cg_lbm_set_phase(self._h, a.ctypes.data_as(C.c_void_p)))
+
+    def set_state(self, fr, fb):
+        """Canonical pre-collision populations (Q, nz, ny, nx): numpy (host) or
+        torch float64 CUDA tensors."""
+        if hasattr(fr, "data_ptr"):
+            assert fr.is_cuda and fb.is_cuda and fr.dtype == fb.dtype
+            fr, fb = fr.contiguous(), fb.contiguous()
+            L.check(L.load().cg_lbm_set_state(self._h, fr.data_ptr(), fb.data_ptr(), 1))
+            return
+        a = np.ascontiguousarray(fr, dtype=np.float64)
+        b = np.ascontiguousarray(fb, dtype=np.float64)
+        L.check(L.load().cg_lbm_set_state(self._h, a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), 0))
+
+    def step(self, n=1):
+        L.check(L.load().cg_lbm_step(self._h, int(n)))
+
+    def sync(self):
+        L.check(L.load().cg_lbm_sync(self._h))
+
+    def observe(self, axis=-1, plane=0, check=True):
+        o = L.Observables()
+        rc = L.load().cg_lbm_observe(self._h, axis, plane, C.byref(o))
+        if check:
+            L.check(rc)
+        return o.as_dict()
+
+    def field(self, name, device=False):
+        """A field of the current state: numpy (host) or a torch CUDA tensor."""
+        which, comps = L.FIELDS[name]
+        comps = self.q if comps == "q" else comps
+        shape = (comps,) + self.shape if comps > 1 else self.shape
+        if device:
+            torch = _torch()
+            out = torch.empty(shape, dtype=torch.float64, device="cuda")
+            L.check(L.load().cg_lbm_get_field(self._h, which, out.data_ptr(), 1))
+            return out
+        out = np.empty(shape, dtype=np.float64)
+        L.check(L.load().cg_lbm_get_field(self._h, which, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def populations(self, device=False):
+        return self.field("f_r", device), self.field("f_b", device)
+
+    # ------------------------------------------------------------ snapshots
+    def save(self):
+        n = L.load().cg_lbm_snapshot_bytes(self._h)
+        buf = np.empty(n, dtype=np.uint8)
+        L.check(L.load().cg_lbm_save(self._h, buf.ctypes.data_as(C.c_void_p)))
+        return buf
+
+    def load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        L.check(L.load().cg_lbm_load(self._h, buf.ctypes.data_as(C.c_void_p)))
+
+    # ---------------------------------------------------------------- timing
+    KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_main")
+
+    def set_timing(self, kernels="all"):
+        """Bracket launches of the named kernels with HIP events ("all", None,
+        or an iterable of names)."""
+        if kernels == "all":
+            mask = -1
+        elif not kernels:
+            mask = 0
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << self.KERNELS.index(k)
+        L.check(L.load().cg_lbm_set_timing(self._h, mask))
+
+    def reset_timing(self):
+        L.check(L.load().cg_lbm_reset_timing(self._h))
+
+    def kernel_times(self):
+        names = (C.c_char * 32 * 16)()
+        counts = (C.c_int64 * 16)()
+        ms = (C.c_double * 16)()
+        n = C.c_int(16)
+        L.check(L.load().cg_lbm_kernel_times(self._h, names, counts, ms, C.byref(n)))
+        return {bytes(names[k]).split(b"\0", 1)[0].decode(): (counts[k], ms[k]) for k in range(n.value)}

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+FP64: the GPU evaluates every operation in the order of the definition with
+no fused multiply-add, so whole runs must agree to 1e-12 relative on rho^r,
+rho^b and u (the bar for the double build).
+FP32: one GPU step from a state is compared with one oracle step from the same
+state (the GPU's FP32 state exported exactly to FP64): 1e-6 relative per step
+on rho^r, rho^b and u; per-colour mass conserved to 1e-6 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from cases import c1_sessile_2d, c2_tube, drop_3d, rel, rock
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-6
+
+
+def _sim(case, kw, precision):
+    from paper_2407_10914_amd.sim import Sim
+
+    s = Sim(case.solid, precision=precision, **kw)
+    s.set_phase(case.phi0)
+    return s
+
+
+def _orc(case, kw, eps="f64"):
+    o = O.OracleSim(case.solid, eps=eps, **kw)
+    o.set_phase(case.phi0)
+    return o
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare_macro(g, o, fluid, tol, tag):
+    gm = dict(rho_r=g.field("rho_r"), rho_b=g.field("rho_b"), u=g.field("u"))
+    om = o.macro()
+    out = {}
+    for k in ("rho_r", "rho_b", "u"):
+        out[k] = rel(gm[k], om[k], fluid)
+    _say(tag, {k: f"{v:.3e}" for k, v in out.items()})
+    for k, v in out.items():
+        assert v <= tol, (tag, k, v)
+    return out
+
+
+def test_c1_sessile_fp64_whole_run():
+    case, kw = c1_sessile_2d()
+    g = _sim(case, kw, "f64")
+    o = _orc(case, kw)
+    fluid = case.solid == 0
+    for t in range(0, 2001, 500):
+        if t:
+            g.step(500)
+            o.step(500)
+        _compare_macro(g, o, fluid, TOL64, f"C1 t={t}")
+    # populations too
+    gr, gb = g.populations()
+    orr, ob = o.get_state()
+    assert rel(gr, orr, fluid) <= TOL64 and rel(gb, ob, fluid) <= TOL64
+
+
+def test_c1_sessile_fp64_stages():
+    case, kw = c1_sessile_2d()
+    g = _sim(case, kw, "f64")
+    o = _orc(case, kw)
+    g.step(37)
+    o.step(37)
+    st = o.stages()
+    info = o.setup_info()
+    keep = info["cls"] >= 1
+    fluid = case.solid == 0
+    assert rel(g.field("phi"), st["phi"], keep) <= TOL64
+    assert rel(g.field("n"), st["n"], keep) <= TOL64
+    assert rel(g.field("C"), st["C"], fluid) <= TOL64
+    assert rel(g.field("kappa"), st["kappa"], fluid) <= TOL64
+    assert rel(g.field("force"), st["F"], fluid) <= TOL64
+
+
+@pytest.mark.parametrize("scheme,theta,drive", [(1, 45.0, "type1"), (2, 45.0, "type1"), (1, 90.0, "type2"),
+                                                (2, 135.0, "type2")])
+def test_c2_tube_fp64_short_tube(scheme, theta, drive):
+    case, kw = c2_tube(scheme=scheme, theta=theta, drive=drive, nz=60, wet_len=20)
+    g = _sim(case, kw, "f64")
+    o = _orc(case, kw)
+    fluid = case.solid == 0
+    for t in (0, 40, 80):
+        if t:
+            g.step(40)
+            o.step(40)
+        _compare_macro(g, o, fluid, TOL64, f"tube s{scheme} {theta} {drive} t={t}")
+    st = o.stages()
+    keep = o.setup_info()["cls"] >= 1
+    assert rel(g.field("n"), st["n"], keep) <= TOL64
+    assert rel(g.field("kappa"), st["kappa"], fluid) <= TOL64
+
+
+def test_c2_tube_fp64_full_size():
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1")
+    g = _sim(case, kw, "f64")
+    o = _orc(case, kw)
+    fluid = case.solid == 0
+    g.step(60)
+    o.step(60)
+    _compare_macro(g, o, fluid, TOL64, "C2 full t=60")
+    a = g.observe(axis=2, plane=200)
+    b = o.observe(axis=2, plane=200)
+    for k in ("mass_r", "mass_b", "vol_r", "vol_b", "flux_t", "sat_w"):
+        assert abs(a[k] - b[k]) <= 1e-12 * max(1.0, abs(b[k])), (k, a[k], b[k])
+
+
+def _fp32_step_parity(case, kw, warm, tag):
+    """Run the GPU FP32 path `warm` steps, export its state exactly, take one
+    oracle step from it and one GPU step, and compare."""
+    g = _sim(case, kw, "f32")
+    fluid = case.solid == 0
+    g.step(warm)
+    fr, fb = g.populations()
+    o = O.OracleSim(case.solid, eps="f32", **kw)
+    o.set_state(fr, fb)
+    g.step(1)
+    o.step(1)
+    out = _compare_macro(g, o, fluid, TOL32, f"{tag} fp32 step {warm}->{warm + 1}")
+    return out
+
+
+def test_fp32_per_step_tube_type1_scheme1():
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1")
+    _fp32_step_parity(case, kw, 200, "C2 S-I")
+
+
+def test_fp32_per_step_tube_type2_scheme2():
+    case, kw = c2_tube(scheme=2, theta=45.0, drive="type2")
+    _fp32_step_parity(case, kw, 200, "C2 S-II T-II")
+
+
+def test_fp32_per_step_rock():
+    case, kw = rock(n=40, buffer=4)
+    _fp32_step_parity(case, kw, 100, "rock40")
+
+
+def test_fp32_per_step_drop_periodic():
+    case, kw = drop_3d()
+    _fp32_step_parity(case, kw, 100, "drop")
+
+
+def test_fp32_mass_conservation_periodic_drop():
+    case, kw = drop_3d(n=24, R=7.0)
+    g = _sim(case, kw, "f32")
+    a = g.observe()
+    g.step(1000)
+    b = g.observe()
+    _say("fp32 mass", b["mass_r"] / a["mass_r"] - 1, b["mass_b"] / a["mass_b"] - 1)
+    assert abs(b["mass_r"] / a["mass_r"] - 1) <= 1e-6
+    assert abs(b["mass_b"] / a["mass_b"] - 1) <= 1e-6
+
+
+def test_fp64_mass_conservation_and_oracle_observables_periodic_drop():
+    case, kw = drop_3d(n=16, R=5.0)
+    g = _sim(case, kw, "f64")
+    o = _orc(case, kw)
+    g.step(100)
+    o.step(100)
+    a, b = g.observe(), o.observe()
+    for k in ("mass_r", "mass_b", "p_in", "p_out", "vol_r", "u_max"):
+        assert abs(a[k] - b[k]) <= 1e-12 * max(1.0, abs(b[k])), (k, a[k], b[k])
