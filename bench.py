@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -145,6 +147,14 @@ def main():
     step_frac = mlups * 1e6 * B_ALG_F32_D3Q19 / (HBM_PEAK_GBS * 1e9)
     del sim
     torch.cuda.empty_cache()
+    if args.copy_calib:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("# copy calibration: 3 x 1 GiB device-to-device copies", file=sys.stderr, flush=True)
+        del x, y
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(case, kw)

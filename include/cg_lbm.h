@@ -221,7 +221,7 @@ cg_status cg_lbm_load(cg_lbm* h, const void* src);
 /* Kernel timing: mask selects the kernels of cg_lbm_step whose every launch is
  * bracketed by HIP events on the handle's stream (bit k = k-th kernel in the
  * order cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n,
- * k_main; -1 = all, 0 = off).  cg_lbm_kernel_times synchronises, then reports
+ * k_curv, k_main; -1 = all, 0 = off).  cg_lbm_kernel_times synchronises, then reports
  * for each kernel its name, launch count and total milliseconds since the
  * last reset (n: in = capacity, out = count). */
 cg_status cg_lbm_set_timing(cg_lbm* h, int mask);

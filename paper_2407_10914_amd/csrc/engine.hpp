@@ -16,19 +16,20 @@
 
 namespace cg {
 
-#define CG_HIP(x)                                  \
-  do {                                             \
-    hipError_t e_ = (x);                           \
-    if (e_ != hipSuccess) {                        \
-      err_ = hipGetErrorString(e_);           \
-      return CG_EHIP;                              \
-    }                                              \
+#define CG_HIP(x)                        \
+  do {                                   \
+    hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) {              \
+      err_ = hipGetErrorString(e_);      \
+      return CG_EHIP;                    \
+    }                                    \
   } while (0)
 
 template <class Real>
 class Engine final : public EngineBase {
   static constexpr bool kF32 = sizeof(Real) == 4;
   static constexpr int BS = 256;
+  using V4 = Vec4<Real>;
 
  public:
   ~Engine() override {
@@ -46,15 +47,14 @@ class Engine final : public EngineBase {
     dim_ = S.dim;
     Q_ = S.Q;
     const size_t Np = (size_t)S.Np, V = (size_t)S.V;
-    const size_t Q = (size_t)S.Q, D = (size_t)S.dim;
+    const size_t Q = (size_t)S.Q;
     auto dev = [&](size_t bytes) -> void* {
       void* p = al_->get(bytes);
       if (p) owned_.push_back(p);
       return p;
     };
     int* nbr = (int*)dev(sizeof(int) * (Q - 1) * Np);
-    int* vox = (int*)dev(sizeof(int) * Np);
-    unsigned* flags = (unsigned*)dev(sizeof(unsigned) * Np);
+    unsigned* vf = (unsigned*)dev(sizeof(unsigned) * Np);
     const size_t nsb = S.sb_vox.size();
     int* sbv = (int*)dev(sizeof(int) * (nsb ? nsb : 1));
     unsigned* sbm = (unsigned*)dev(sizeof(unsigned) * (nsb ? nsb : 1));
@@ -62,20 +62,20 @@ class Engine final : public EngineBase {
     Real* ct = (Real*)dev(sizeof(Real) * Np);
     Real* stt = (Real*)dev(sizeof(Real) * Np);
     Real* phi = (Real*)dev(sizeof(Real) * V);
-    Real* ng = (Real*)dev(sizeof(Real) * D * V);
-    Real* cv = (Real*)dev(sizeof(Real) * D * Np);
+    V4* ng = (V4*)dev(sizeof(V4) * V);
+    V4* cv = (V4*)dev(sizeof(V4) * Np);
+    V4* fv = (V4*)dev(sizeof(V4) * Np);
     const int nb = (S.N + BS - 1) / BS;
     obs_part_ = (double*)dev(sizeof(double) * (size_t)kObsN * (nb + 1));
     obs_out_ = (double*)dev(sizeof(double) * kObsN);
     if (kF32) {
       for (int k = 0; k < 2; ++k) {
         T_[k] = (float*)dev(sizeof(float) * Q * Np);
-        A_[k] = (float*)dev(sizeof(float) * Np);
-        Cc_[k] = (float*)dev(sizeof(float) * D * Np);
+        AC_[k] = (float4*)dev(sizeof(float4) * Np);
       }
       pre_r_ = (Real*)dev(sizeof(Real) * Q * Np);
       pre_x_ = (Real*)dev(sizeof(Real) * Q * Np);
-      state_bytes_ = sizeof(float) * (Q + 1 + D) * Np;
+      state_bytes_ = sizeof(float) * Q * Np + sizeof(float4) * Np;
     } else {
       for (int k = 0; k < 2; ++k) {
         fr_[k] = (Real*)dev(sizeof(Real) * Q * Np);
@@ -89,8 +89,8 @@ class Engine final : public EngineBase {
         return CG_ENOMEM;
       }
     // upload
-    std::vector<int> voxp(Np, 0);
-    std::copy(S.node_vox.begin(), S.node_vox.end(), voxp.begin());
+    std::vector<unsigned> vfp(Np, 0u);
+    for (int n = 0; n < S.N; ++n) vfp[n] = (unsigned)S.node_vox[n] | (S.flags[n] << kVoxBits);
     std::vector<Real> nwr(3 * Np), ctr(Np), str(Np);
     for (size_t i = 0; i < 3 * Np; ++i) nwr[i] = (Real)S.nw[i];
     for (size_t i = 0; i < Np; ++i) {
@@ -102,22 +102,22 @@ class Engine final : public EngineBase {
       if (e == hipSuccess && bytes) e = hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
     };
     up(nbr, S.nbr.data(), sizeof(int) * (Q - 1) * Np);
-    up(vox, voxp.data(), sizeof(int) * Np);
-    up(flags, S.flags.data(), sizeof(unsigned) * Np);
+    up(vf, vfp.data(), sizeof(unsigned) * Np);
     up(sbv, S.sb_vox.data(), sizeof(int) * nsb);
     up(sbm, S.sb_mask.data(), sizeof(unsigned) * nsb);
     up(nw, nwr.data(), sizeof(Real) * 3 * Np);
     up(ct, ctr.data(), sizeof(Real) * Np);
     up(stt, str.data(), sizeof(Real) * Np);
     if (e == hipSuccess) e = hipMemset(phi, 0, sizeof(Real) * V);
-    if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(Real) * D * V);
-    if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(Real) * D * Np);
+    if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(V4) * V);
+    if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(V4) * Np);
+    if (e == hipSuccess) e = hipMemset(fv, 0, sizeof(V4) * Np);
     if (e != hipSuccess) {
       *err = std::string("upload failed: ") + hipGetErrorString(e);
       return CG_EHIP;
     }
-    G_ = Geo<Real>{nbr, vox, flags, sbv, sbm, nw, ct, stt};
-    R_ = Grids<Real>{phi, ng, cv};
+    G_ = Geo<Real>{nbr, vf, sbv, sbm, nw, ct, stt};
+    R_ = Grids<Real>{phi, ng, cv, fv};
     nsb_ = (int)nsb;
     dev_bytes_ = al_->total;
     // rest state, all fluid b
@@ -133,9 +133,9 @@ class Engine final : public EngineBase {
     Real* x = pre_x();
     if (e == hipSuccess) {
       if (dim_ == 3)
-        launch(-1, k_set_phase<Real, 3>, P_.N, P_, d, r, x);
+        launch(-1, k_set_phase<Real, 3>, P_.N, P_, (const double*)d, r, x);
       else
-        launch(-1, k_set_phase<Real, 2>, P_.N, P_, d, r, x);
+        launch(-1, k_set_phase<Real, 2>, P_.N, P_, (const double*)d, r, x);
       e = hipStreamSynchronize(stream_);
     }
     al_->put(d);
@@ -199,12 +199,11 @@ class Engine final : public EngineBase {
   }
 
   int phi_grid(double* dst) override {
-    if (dim_ == 3) {
+    if (dim_ == 3)
       front<3>(2);
-    } else {
+    else
       front<2>(2);
-    }
-    launch(-1, k_grid_copy<Real>, P_.V, P_.V, (const int*)nullptr, 1, P_.V, (const Real*)R_.phi, dst);
+    launch(-1, k_grid_copy<Real>, P_.V, P_.V, (const Real*)R_.phi, dst);
     CG_HIP(hipGetLastError());
     CG_HIP(hipStreamSynchronize(stream_));
     return CG_OK;
@@ -215,7 +214,7 @@ class Engine final : public EngineBase {
       front<3>(4);
     else
       front<2>(4);
-    launch(-1, k_grid_copy<Real>, P_.V, P_.V, (const int*)nullptr, dim_, P_.V, (const Real*)R_.n, dst);
+    launch(-1, k_grid_copy4<Real>, P_.V, P_.V, (const V4*)R_.n, dst);
     CG_HIP(hipGetLastError());
     CG_HIP(hipStreamSynchronize(stream_));
     return CG_OK;
@@ -245,7 +244,7 @@ class Engine final : public EngineBase {
   }
 
   // snapshot: header (time, pre flag, cur) + the live state buffers
-  size_t snapshot_bytes() const override { return 64 + state_bytes_ + (kF32 ? 0 : 0) + pre_bytes(); }
+  size_t snapshot_bytes() const override { return 64 + state_bytes_ + pre_bytes(); }
   int save(void* dst) override {
     CG_HIP(hipStreamSynchronize(stream_));
     char* p = (char*)dst;
@@ -317,8 +316,7 @@ class Engine final : public EngineBase {
   Real* fr_[2] = {nullptr, nullptr};
   Real* fb_[2] = {nullptr, nullptr};
   float* T_[2] = {nullptr, nullptr};
-  float* A_[2] = {nullptr, nullptr};
-  float* Cc_[2] = {nullptr, nullptr};
+  float4* AC_[2] = {nullptr, nullptr};
   Real* pre_r_ = nullptr;
   Real* pre_x_ = nullptr;
   double* obs_part_ = nullptr;
@@ -342,9 +340,8 @@ class Engine final : public EngineBase {
   Real* pre_x() { return kF32 ? pre_x_ : fb_[cur_]; }
 
   std::vector<std::pair<void*, size_t>> state_segments(int c) {
-    const size_t Np = P_.Np, Q = Q_, D = dim_;
-    if (kF32)
-      return {{T_[c], sizeof(float) * Q * Np}, {A_[c], sizeof(float) * Np}, {Cc_[c], sizeof(float) * D * Np}};
+    const size_t Np = P_.Np, Q = Q_;
+    if (kF32) return {{T_[c], sizeof(float) * Q * Np}, {AC_[c], sizeof(float4) * Np}};
     return {{fr_[c], sizeof(Real) * Q * Np}, {fb_[c], sizeof(Real) * Q * Np}};
   }
 
@@ -396,7 +393,7 @@ class Engine final : public EngineBase {
   template <int D>
   auto in_post() const {
     if constexpr (kF32)
-      return InCompact<D>{T_[cur_], A_[cur_], Cc_[cur_], P_.Np, (float)P_.rho0};
+      return InCompact<D>{T_[cur_], AC_[cur_], P_.Np, (float)P_.rho0};
     else
       return InCanon<Real, D>{fr_[cur_], fb_[cur_], P_.Np};
   }
@@ -411,18 +408,21 @@ class Engine final : public EngineBase {
   auto out_next() const {
     const int nx = cur_ ^ 1;
     if constexpr (kF32)
-      return OutCompact<D>{T_[nx], A_[nx], Cc_[nx], P_.Np};
+      return OutCompact<D>{T_[nx], AC_[nx], P_.Np};
     else
       return OutCanon<Real, D>{fr_[nx], fb_[nx], P_.Np};
   }
 
-  // phase field (and optionally the normals): stages 1..upto of the step
+  // stages 1..upto of the step before the fused kernel: phase field (1),
+  // phase into the solid (2), normals with wetting (3), normals into the
+  // solid (4), curvature and force (5)
   template <int D, class In>
   void front_with(const In& in, int upto) {
     launch(K_PHASE, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
     if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
     if (upto >= 3) launch(K_NORMAL, k_normal<Real, D>, P_.N, P_, G_, R_);
     if (upto >= 4 && nsb_) launch(K_SB_N, k_sb_n<Real, D>, nsb_, P_, G_, R_);
+    if (upto >= 5) launch(K_CURV, k_curv<Real, D>, P_.N, P_, G_, R_);
   }
   template <int D>
   void front(int upto) {
@@ -432,27 +432,26 @@ class Engine final : public EngineBase {
       front_with<D>(in_post<D>(), upto);
   }
 
+  template <int D, class In>
+  void step_with(const In& in) {
+    auto out = out_next<D>();
+    front_with<D>(in, 5);
+    launch(K_MAIN, k_main<Real, D, BS, MODE_STEP, In, decltype(out)>, P_.N, P_, G_, R_, in, out, MacroOut{},
+           ObsOut{});
+  }
   template <int D>
   void one_step() {
-    auto out = out_next<D>();
-    if (pre_) {
-      auto in = in_pre<D>();
-      front_with<D>(in, 4);
-      launch(K_MAIN, k_main<Real, D, BS, MODE_STEP, decltype(in), decltype(out)>, P_.N, P_, G_, R_, in, out,
-             MacroOut{}, ObsOut{});
-    } else {
-      auto in = in_post<D>();
-      front_with<D>(in, 4);
-      launch(K_MAIN, k_main<Real, D, BS, MODE_STEP, decltype(in), decltype(out)>, P_.N, P_, G_, R_, in, out,
-             MacroOut{}, ObsOut{});
-    }
+    if (pre_)
+      step_with<D>(in_pre<D>());
+    else
+      step_with<D>(in_post<D>());
     cur_ ^= 1;
     pre_ = false;
   }
 
   template <int D, class In>
   void macro_with(const In& in, MacroOut mo) {
-    front_with<D>(in, 4);
+    front_with<D>(in, 5);
     auto out = out_next<D>();
     launch(-1, k_main<Real, D, BS, MODE_MACRO, In, decltype(out)>, P_.N, P_, G_, R_, in, out, mo, ObsOut{});
   }
@@ -466,12 +465,13 @@ class Engine final : public EngineBase {
 
   template <int D, class In>
   void obs_with(const In& in) {
-    front_with<D>(in, 4);
+    front_with<D>(in, 5);
     auto out = out_next<D>();
     const int nb = (P_.N + BS - 1) / BS;
     launch(-1, k_main<Real, D, BS, MODE_OBS, In, decltype(out)>, P_.N, P_, G_, R_, in, out, MacroOut{},
            ObsOut{obs_part_});
-    hipLaunchKernelGGL(k_obs_final<Real>, dim3(1), dim3(64), 0, stream_, (const double*)obs_part_, nb, obs_out_);
+    hipLaunchKernelGGL(k_obs_final<Real>, dim3(kObsN), dim3(256), 0, stream_, (const double*)obs_part_, nb,
+                       obs_out_);
   }
   template <int D>
   void run_obs() {

@@ -1,33 +1,56 @@
 // __global__ kernels of the time step, observables and state transfer.
 // Instantiated per precision in kernels_f64.hip / kernels_f32.hip.
+//
+// Order within one step: k_phase -> k_sb_phi -> k_normal -> k_sb_n -> k_curv
+// -> k_main.  Each kernel needs the previous one complete over the whole
+// grid (stencils of radius 1 on the previous output).
 #pragma once
 
 #include "step.hpp"
 
 namespace cg {
 
+__device__ __forceinline__ int vox_of(unsigned vf) { return (int)(vf & kVoxMask); }
+__device__ __forceinline__ unsigned flags_of(unsigned vf) { return vf >> kVoxBits; }
+
 // ------------------------------------------------------------------ k_phase
 // Densities and phase field at every fluid node, Eqs. (7)-(9); inlet nodes take
 // phi_in (Sec. II.D.1), outlet nodes the phase one node upstream (Eq. 39).
+// The sums are taken in double for either state layout.
 template <class Real, int D, class In>
 __global__ void k_phase(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
+  using CT = double;
   const int n = node_id();
   if (n >= P.N) return;
-  const unsigned fl = G.flags[n];
-  Real phi;
+  const unsigned vf = G.vf[n];
+  const unsigned fl = flags_of(vf);
+  CT phi;
   if (fl & FL_IN) {
-    phi = (Real)P.phi_in;
+    phi = P.phi_in;
   } else {
     const int src = (fl & FL_OUT) ? G.nbr[(kDirZp - 1) * P.Np + n] : n;
     Real fr[Q], fx[Q];
     load_node<D>(in, G.nbr, P.Np, src, fr, fx);
-    Real rr, rb, rho, drho;
-    node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
+    CT rr, rb, rho;
+    if constexpr (kDev) {
+      CT a = fr[0], t = (CT)Lat<D>::w(0) * P.rho0 + (CT)fx[0];
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        a = a + (CT)fr[i];
+        t = t + ((CT)Lat<D>::w(i) * P.rho0 + (CT)fx[i]);
+      });
+      rr = a;
+      rho = t;
+      rb = t - a;
+    } else {
+      CT drho;
+      node_moments<D, kDev>(fr, fx, (CT)P.rho0, rr, rb, rho, drho);
+    }
     phi = (rr - rb) / rho;
   }
-  R.phi[G.vox[n]] = phi;
+  R.phi[vox_of(vf)] = (Real)phi;
 }
 
 // ----------------------------------------------------------------- k_sb_phi
@@ -39,12 +62,13 @@ __global__ void k_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R) {
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
+  const bool face = m & 1u;
   Real num = Real(0), den = Real(0);
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     if (m & (1u << i)) {
       constexpr double w = Lat<D>::w(i);
-      const int y = nb_slow(P, v, Lat<D>::e(i, 0), Lat<D>::e(i, 1), Lat<D>::e(i, 2));
+      const int y = nb_vox<D, i>(P, v, face);
       num = num + (Real)w * R.phi[y];
       den = den + (Real)w;
     }
@@ -54,59 +78,68 @@ __global__ void k_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R) {
 
 // ----------------------------------------------------------------- k_normal
 // Colour gradient, Eq. (6), unit normal, Eq. (27), wetting at the fluid
-// boundary points (Sec. II.B.3 step 3) keeping |C|.
+// boundary points (Sec. II.B.3 step 3) keeping |C|.  Double arithmetic for
+// either layout.
 template <class Real, int D>
 __global__ void k_normal(StepParams P, Geo<Real> G, Grids<Real> R) {
   constexpr int Q = Lat<D>::Q;
+  using CT = double;
   const int n = node_id();
   if (n >= P.N) return;
-  const int v = G.vox[n];
-  const unsigned fl = G.flags[n];
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const unsigned fl = flags_of(vf);
   const bool face = fl & FL_FACE;
   Real ph[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     if constexpr (i > 0) ph[i] = R.phi[nb_vox<D, i>(P, v, face)];
   });
-  Real C[3] = {Real(0), Real(0), Real(0)};
+  CT C[3] = {CT(0), CT(0), CT(0)};
   unroll<D>([&](auto A_) {
     constexpr int a = A_;
-    Real s = Real(0);
+    CT s = CT(0);
     bool first = true;
     unroll<Q>([&](auto I) {
       constexpr int i = I;
       constexpr int e = Lat<D>::e(i, a);
       if constexpr (e != 0) {
         constexpr double we = Lat<D>::w(i) * e;
-        const Real t = (Real)we * ph[i];
+        const CT t = (CT)we * (CT)ph[i];
         s = first ? t : s + t;
         first = false;
       }
     });
-    C[a] = Real(3) * s;
+    C[a] = CT(3) * s;
   });
-  const Real cm = sqrt(dotv<Real, D>(C, C));
-  Real nn[3] = {Real(0), Real(0), Real(0)};
-  if (cm > (Real)P.eps_c) {
+  const CT cm = sqrt(dotv<CT, D>(C, C));
+  CT nn[3] = {CT(0), CT(0), CT(0)};
+  if (cm > (CT)P.eps_c) {
 #pragma unroll
     for (int a = 0; a < D; ++a) nn[a] = C[a] / cm;
     if ((fl & FL_WET) && P.scheme != 0) {
-      Real w3[3];
+      CT w3[3];
 #pragma unroll
-      for (int a = 0; a < D; ++a) w3[a] = G.nw[a * P.Np + n];
+      for (int a = 0; a < D; ++a) w3[a] = (CT)G.nw[a * P.Np + n];
       if (P.scheme == 1)
-        scheme1<Real, D>(nn, w3, G.cos_t[n], (fl & FL_S1POS) ? Real(1) : Real(-1), (Real)P.eps_f, (Real)P.eps_v);
+        scheme1<CT, D>(nn, w3, (CT)G.cos_t[n], (fl & FL_S1POS) ? CT(1) : CT(-1), (CT)P.eps_f, (CT)P.eps_v);
       else
-        scheme2<Real, D>(nn, w3, G.cos_t[n], G.sin_t[n], (Real)P.eps_v);
+        scheme2<CT, D>(nn, w3, (CT)G.cos_t[n], (CT)G.sin_t[n], (CT)P.eps_v);
 #pragma unroll
       for (int a = 0; a < D; ++a) C[a] = cm * nn[a];
     }
   }
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    R.n[a * P.V + v] = nn[a];
-    R.c[a * P.Np + n] = C[a];
-  }
+  Vec4<Real> nv, cv;
+  nv.x = (Real)nn[0];
+  nv.y = (Real)nn[1];
+  nv.z = (Real)nn[2];
+  nv.w = Real(0);
+  cv.x = (Real)C[0];
+  cv.y = (Real)C[1];
+  cv.z = (Real)C[2];
+  cv.w = Real(0);
+  R.n[v] = nv;
+  R.c[n] = cv;
 }
 
 // ------------------------------------------------------------------- k_sb_n
@@ -118,20 +151,86 @@ __global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
+  const bool face = m & 1u;
   Real num[3] = {Real(0), Real(0), Real(0)};
   Real den = Real(0);
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     if (m & (1u << i)) {
       constexpr double w = Lat<D>::w(i);
-      const int y = nb_slow(P, v, Lat<D>::e(i, 0), Lat<D>::e(i, 1), Lat<D>::e(i, 2));
+      const Vec4<Real> q = R.n[nb_vox<D, i>(P, v, face)];
+      const Real qq[3] = {q.x, q.y, q.z};
 #pragma unroll
-      for (int a = 0; a < D; ++a) num[a] = num[a] + (Real)w * R.n[a * P.V + y];
+      for (int a = 0; a < D; ++a) num[a] = num[a] + (Real)w * qq[a];
       den = den + (Real)w;
     }
   });
+  Vec4<Real> o;
+  o.x = num[0] / den;
+  o.y = num[1] / den;
+  o.z = D == 3 ? num[2] / den : Real(0);
+  o.w = Real(0);
+  R.n[v] = o;
+}
+
+// ------------------------------------------------------------------- k_curv
+// Curvature, Eq. (12), from the isotropic derivatives of n (same stencil as
+// Eq. 6), and the force F = 1/2 sigma kappa C (Eq. 5) + rho_o g (Eq. 36).
+template <class Real, int D>
+__global__ void k_curv(StepParams P, Geo<Real> G, Grids<Real> R) {
+  constexpr int Q = Lat<D>::Q;
+  using CT = double;
+  const int n = node_id();
+  if (n >= P.N) return;
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const bool face = flags_of(vf) & FL_FACE;
+  Vec4<Real> nb[Q];
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    if constexpr (i > 0) nb[i] = R.n[nb_vox<D, i>(P, v, face)];
+  });
+  const Vec4<Real> self = R.n[v];
+  CT d[3][3];
+  unroll<D>([&](auto B_) {
+    constexpr int b = B_;
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      CT s = CT(0);
+      bool first = true;
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        constexpr int e = Lat<D>::e(i, b);
+        if constexpr (e != 0) {
+          constexpr double we = Lat<D>::w(i) * e;
+          const Real na = a == 0 ? nb[i].x : (a == 1 ? nb[i].y : nb[i].z);
+          const CT t = (CT)we * (CT)na;
+          s = first ? t : s + t;
+          first = false;
+        }
+      });
+      d[b][a] = CT(3) * s;
+    });
+  });
+  const CT nx_ = self.x, ny_ = self.y, nz_ = self.z;
+  CT k;
+  if constexpr (D == 3) {
+    k = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (nz_ * nz_ - CT(1)) * d[2][2] +
+        (d[1][0] + d[0][1]) * nx_ * ny_ + (d[2][0] + d[0][2]) * nx_ * nz_ + (d[1][2] + d[2][1]) * nz_ * ny_;
+  } else {
+    k = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (d[1][0] + d[0][1]) * nx_ * ny_;
+  }
+  const Vec4<Real> c = R.c[n];
+  const CT C[3] = {(CT)c.x, (CT)c.y, (CT)c.z};
+  CT F[3] = {CT(0), CT(0), CT(0)};
 #pragma unroll
-  for (int a = 0; a < D; ++a) R.n[a * P.V + v] = num[a] / den;
+  for (int a = 0; a < D; ++a) F[a] = P.half_sigma * k * C[a] + P.rg[a];
+  Vec4<Real> o;
+  o.x = (Real)F[0];
+  o.y = (Real)F[1];
+  o.z = (Real)F[2];
+  o.w = (Real)k;
+  R.f[n] = o;
 }
 
 // ------------------------------------------------------------------- k_main
@@ -181,14 +280,15 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return t;
 }
 
-// Pull, faces, curvature, force, velocity, rates, collision, recolouring,
-// store (MODE_STEP); or the macroscopic fields (MODE_MACRO); or the
-// observable reductions (MODE_OBS).
+// Pull, faces, velocity, rates, collision, recolouring, store (MODE_STEP);
+// or the macroscopic fields (MODE_MACRO); or the observable reductions
+// (MODE_OBS).
 template <class Real, int D, int BS, int Mode, class In, class Out>
 __global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Real> R, In in, Out out,
                                              MacroOut mo, ObsOut oo) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
+  using CT = double;
   const int n = node_id();
   const bool active = n < P.N;
   double o[kObsN];
@@ -197,9 +297,9 @@ __global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Re
     for (int k = 0; k < kObsN; ++k) o[k] = 0.0;
   }
   if (active) {
-    const int v = G.vox[n];
-    const unsigned fl = G.flags[n];
-    const bool face = fl & FL_FACE;
+    const unsigned vf = G.vf[n];
+    const int v = vox_of(vf);
+    const unsigned fl = flags_of(vf);
     Real fr[Q], fx[Q];
     load_node<D>(in, G.nbr, P.Np, n, fr, fx);
     if constexpr (In::kPull) {
@@ -208,94 +308,66 @@ __global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Re
     Real rr, rb, rho, drho;
     node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
     const Real phi = R.phi[v];
-    // curvature, Eq. (12), from the isotropic derivatives of n
-    Real nb[D][Q];
-    unroll<Q>([&](auto I) {
-      constexpr int i = I;
-      if constexpr (i > 0) {
-        const int y = nb_vox<D, i>(P, v, face);
-#pragma unroll
-        for (int a = 0; a < D; ++a) nb[a][i] = R.n[a * P.V + y];
-      }
-    });
-    Real d[3][3];
-    unroll<D>([&](auto B_) {
-      constexpr int b = B_;
-      unroll<D>([&](auto A_) {
-        constexpr int a = A_;
-        Real s = Real(0);
-        bool first = true;
-        unroll<Q>([&](auto I) {
-          constexpr int i = I;
-          constexpr int e = Lat<D>::e(i, b);
-          if constexpr (e != 0) {
-            constexpr double we = Lat<D>::w(i) * e;
-            const Real t = (Real)we * nb[a][i];
-            s = first ? t : s + t;
-            first = false;
-          }
-        });
-        d[b][a] = Real(3) * s;
-      });
-    });
-    Real nx_ = R.n[v], ny_ = R.n[P.V + v], nz_ = Real(0);
-    if constexpr (D == 3) nz_ = R.n[2 * P.V + v];
-    Real k;
-    if constexpr (D == 3) {
-      k = (nx_ * nx_ - Real(1)) * d[0][0] + (ny_ * ny_ - Real(1)) * d[1][1] + (nz_ * nz_ - Real(1)) * d[2][2] +
-          (d[1][0] + d[0][1]) * nx_ * ny_ + (d[2][0] + d[0][2]) * nx_ * nz_ + (d[1][2] + d[2][1]) * nz_ * ny_;
-    } else {
-      k = (nx_ * nx_ - Real(1)) * d[0][0] + (ny_ * ny_ - Real(1)) * d[1][1] + (d[1][0] + d[0][1]) * nx_ * ny_;
-    }
-    // force, Eq. (5) + rho_o g (Eq. 36); velocity, Eq. (22) (deviation layout:
-    // the density of the momentum balance is rho0 + sum g)
-    const Real rho_u = kDev ? (Real)P.rho0 + drho : rho;
-    Real C[3] = {Real(0), Real(0), Real(0)}, F[3] = {Real(0), Real(0), Real(0)}, u[3] = {Real(0), Real(0), Real(0)};
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      C[a] = R.c[a * P.Np + n];
-      F[a] = (Real)P.half_sigma * k * C[a] + (Real)P.rg[a];
-    }
+    const Vec4<Real> f4 = R.f[n];
+    const Vec4<Real> n4 = R.n[v];
+    // velocity, Eq. (22), in the storage precision for the collision and in
+    // double for the reported fields; the deviation layout balances momentum
+    // with rho0 + sum g
+    using UT = std::conditional_t<Mode == MODE_STEP, Real, CT>;
+    const UT F[3] = {(UT)f4.x, (UT)f4.y, (UT)f4.z};
+    const UT rho_u = kDev ? (UT)P.rho0 + (UT)drho : (UT)rho;
+    UT u[3] = {UT(0), UT(0), UT(0)};
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
-      Real j = Real(0);
+      UT j = UT(0);
       bool first = true;
       unroll<Q>([&](auto I) {
         constexpr int i = I;
         constexpr int e = Lat<D>::e(i, a);
         if constexpr (e != 0) {
-          const Real t = e == 1 ? fx[i] : -fx[i];
+          const UT t = e == 1 ? (UT)fx[i] : -(UT)fx[i];
           j = first ? t : j + t;
           first = false;
         }
       });
-      u[a] = (j + Real(0.5) * F[a]) / rho_u;
+      u[a] = (j + UT(0.5) * F[a]) / rho_u;
     });
     if constexpr (Mode == MODE_STEP) {
       Real s_nu, s_q;
       rates(P, phi, s_nu, s_q);
+      Real ur[3], Fr[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        ur[a] = (Real)u[a];
+        Fr[a] = (Real)F[a];
+      }
       if constexpr (D == 3) {
-        if (P.collision == 1)
-          collide_mrt<!kDev>(fx, drho, (Real)P.rho0, u, F, s_nu, s_q);
-        else
-          collide_bgk<D>(fx, drho, (Real)P.rho0, u, F, s_nu);
+        if (P.collision == 1) {
+          if constexpr (kDev)
+            collide_mrt_fast(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
+          else
+            collide_mrt<true>(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
+        } else
+          collide_bgk<D>(fx, drho, (Real)P.rho0, ur, Fr, s_nu);
       } else {
-        collide_bgk<D>(fx, drho, (Real)P.rho0, u, F, s_nu);
+        collide_bgk<D>(fx, drho, (Real)P.rho0, ur, Fr, s_nu);
       }
       // recolouring, Eqs. (20)-(21)
       const Real rsum = rr + rb;
       const Real a = rr / rsum;
       const Real b = rr * rb / rsum;
       if constexpr (kDev) {
-        out.A[n] = a;
         const Real bb = (Real)P.beta * b;
-        out.Cc[n] = bb * nx_;
-        out.Cc[out.Np + n] = bb * ny_;
-        if constexpr (D == 3) out.Cc[2 * out.Np + n] = bb * nz_;
+        float4 ac;
+        ac.x = a;
+        ac.y = bb * n4.x;
+        ac.z = bb * n4.y;
+        ac.w = D == 3 ? bb * n4.z : 0.f;
+        out.AC[n] = ac;
 #pragma unroll
         for (int i = 0; i < Q; ++i) out.T[i * out.Np + n] = fx[i];
       } else {
-        const Real nvec[3] = {nx_, ny_, nz_};
+        const Real nvec[3] = {n4.x, n4.y, n4.z};
         unroll<Q>([&](auto I) {
           constexpr int i = I;
           const Real fpp = fx[i];
@@ -322,15 +394,17 @@ __global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Re
         });
       }
     } else if constexpr (Mode == MODE_MACRO) {
+      const Vec4<Real> c4 = R.c[n];
       if (mo.rho_r) mo.rho_r[v] = (double)rr;
       if (mo.rho_b) mo.rho_b[v] = (double)rb;
       if (mo.phi) mo.phi[v] = (double)phi;
-      if (mo.kappa) mo.kappa[v] = (double)k;
+      if (mo.kappa) mo.kappa[v] = (double)f4.w;
+      const double cc[3] = {(double)c4.x, (double)c4.y, (double)c4.z};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        if (mo.u) mo.u[a * P.V + v] = (double)u[a];
-        if (mo.force) mo.force[a * P.V + v] = (double)F[a];
-        if (mo.cvec) mo.cvec[a * P.V + v] = (double)C[a];
+        if (mo.u) mo.u[(size_t)a * P.V + v] = (double)u[a];
+        if (mo.force) mo.force[(size_t)a * P.V + v] = (double)F[a];
+        if (mo.cvec) mo.cvec[(size_t)a * P.V + v] = cc[a];
       }
     } else {
       const double a = rr, b = rb, ph = phi;
@@ -384,31 +458,40 @@ __global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Re
   }
 }
 
-// Second pass of the observables: partial sums in block order (deterministic).
-// (templated only so that each precision's unit owns its instance)
+// Second pass of the observables: one block per accumulator; each thread
+// reduces a fixed strided subset in order, then a fixed tree (deterministic).
 template <class Real>
 __global__ void k_obs_final(const double* part, int nblocks, double* out) {
-  const int q = threadIdx.x;
-  if (q >= kObsN) return;
+  const int q = blockIdx.x;
+  __shared__ double sh[256];
   double t = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     const double x = part[b * kObsN + q];
     t = (q == 10) ? fmax(t, x) : t + x;
   }
-  out[q] = t;
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      sh[threadIdx.x] = (q == 10) ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = sh[0];
 }
 
 // -------------------------------------------------------- state transfer
 // Canonical pre-collision populations of the current state, as FP64 dense
-// [Q][V] arrays (pull, bounce-back and faces applied).
+// [Q][V] arrays (pull, bounce-back and faces applied; the compact layout is
+// rebuilt in double).
 template <class Real, int D, class In>
 __global__ void k_export(StepParams P, Geo<Real> G, Grids<Real> R, In in, double* fr_out, double* fb_out) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   const int n = node_id();
   if (n >= P.N) return;
-  const int v = G.vox[n];
-  const unsigned fl = G.flags[n];
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const unsigned fl = flags_of(vf);
   double fr[Q], fx[Q];
   load_node<D>(in, G.nbr, P.Np, n, fr, fx);
   if constexpr (In::kPull) {
@@ -428,7 +511,7 @@ __global__ void k_import(StepParams P, Geo<Real> G, const double* fr, const doub
   constexpr bool kDev = sizeof(Real) == 4;
   const int n = node_id();
   if (n >= P.N) return;
-  const int v = G.vox[n];
+  const int v = vox_of(G.vf[n]);
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     const double a = fr[(size_t)i * P.V + v], b = fb[(size_t)i * P.V + v];
@@ -457,21 +540,23 @@ __global__ void k_set_phase(StepParams P, const double* phi_nodes, Real* r_out, 
   });
 }
 
-// Scatter a per-node array into a dense FP64 voxel array (dense must be zeroed).
+// Dense voxel grid (scalar) -> dense FP64 array.
 template <class Real>
-__global__ void k_scatter(int N, int Np, int comps, int V, const int* vox, const Real* src, double* dst) {
-  const int n = node_id();
-  if (n >= N) return;
-  for (int c = 0; c < comps; ++c) dst[(size_t)c * V + vox[n]] = (double)src[c * Np + n];
-}
-
-// Copy a dense voxel grid at the listed voxels to a dense FP64 array.
-template <class Real>
-__global__ void k_grid_copy(int count, const int* list, int comps, int V, const Real* grid, double* dst) {
+__global__ void k_grid_copy(int count, const Real* grid, double* dst) {
   const int n = node_id();
   if (n >= count) return;
-  const int v = list ? list[n] : n;
-  for (int c = 0; c < comps; ++c) dst[(size_t)c * V + v] = (double)grid[(size_t)c * V + v];
+  dst[n] = (double)grid[n];
+}
+
+// Dense voxel grid of 4-vectors -> dense FP64 [3][V] array.
+template <class Real>
+__global__ void k_grid_copy4(int count, const Vec4<Real>* grid, double* dst) {
+  const int n = node_id();
+  if (n >= count) return;
+  const Vec4<Real> q = grid[n];
+  dst[n] = (double)q.x;
+  dst[(size_t)count + n] = (double)q.y;
+  dst[2 * (size_t)count + n] = (double)q.z;
 }
 
 }  // namespace cg

@@ -120,8 +120,8 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
     return CG_EINVAL;
   }
   const long Vl = (long)b.nx * b.ny * b.nz;
-  if (Vl * 3 >= (1L << 31)) {
-    *err = "voxel count too large for 32-bit indexing";
+  if (Vl > (long)kVoxMask + 1) {
+    *err = "more than 2^27 voxels: the per-node word holds a 27-bit voxel index";
     return CG_EUNSUPPORTED;
   }
   if (b.open_z && (g.dim != 3 || b.per[2] || b.nz < 3)) {
@@ -198,6 +198,12 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
       }
     }
     if (sb) {
+      // bit 0: the voxel lies on a domain face (its stencil needs wrap/clamp)
+      int c[3];
+      b.xyz(v, c);
+      if (c[0] == 0 || c[0] == b.nx - 1 || c[1] == 0 || c[1] == b.ny - 1 ||
+          (g.dim == 3 && (c[2] == 0 || c[2] == b.nz - 1)))
+        mask |= 1u;
       S.sb_vox.push_back(v);
       S.sb_mask.push_back(mask);
     }

@@ -42,6 +42,9 @@ enum : unsigned {
   FL_OUT = 8u,    // Zou-He outlet node (z = nz-1)
   FL_S1POS = 16u  // Scheme-I secant start uses s = +1
 };
+// per-node word: voxel index in the low kVoxBits bits, flags above
+constexpr int kVoxBits = 27;
+constexpr unsigned kVoxMask = (1u << kVoxBits) - 1u;
 
 // number of observable accumulators (see k_main, MODE_OBS)
 constexpr int kObsN = 15;
@@ -71,12 +74,25 @@ struct StepParams {
 };
 
 template <class Real>
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+  using type = float4;
+};
+template <>
+struct Vec4T<double> {
+  using type = double4;
+};
+template <class Real>
+using Vec4 = typename Vec4T<Real>::type;
+
+template <class Real>
 struct Geo {
   const int* nbr;          // [Q-1][Np]: source of direction i (i >= 1) or a code
-  const int* vox;          // [Np] voxel index
-  const unsigned* flags;   // [Np]
+  const unsigned* vf;      // [Np] voxel index | flags << kVoxBits
   const int* sb_vox;       // [nsb]
-  const unsigned* sb_mask; // [nsb] bit i: the link s + e_i ends on a fluid voxel in the domain
+  const unsigned* sb_mask; // [nsb] bit i: the link s + e_i ends on a fluid voxel in
+                           // the domain; bit 0: the voxel lies on a domain face
   const Real* nw;          // [3][Np] wall normal (unit)
   const Real* cos_t;       // [Np]
   const Real* sin_t;       // [Np]
@@ -84,9 +100,10 @@ struct Geo {
 
 template <class Real>
 struct Grids {
-  Real* phi;   // [V]
-  Real* n;     // [D][V]
-  Real* c;     // [D][Np] colour gradient after wetting
+  Real* phi;        // [V] phase field (fluid nodes and solid boundary points)
+  Vec4<Real>* n;    // [V] interface normal after wetting (xyz), fluid and S_b
+  Vec4<Real>* c;    // [Np] colour gradient after wetting (xyz)
+  Vec4<Real>* f;    // [Np] force (xyz) and curvature (w)
 };
 
 // ------------------------------------------------------------------- helpers
@@ -157,27 +174,28 @@ struct InCanon {
 };
 
 // Compact post-collision state (float path); x = g = f^t - w rho0.
+// AC[s] = (a, c_x, c_y, c_z) with a = rho^r/rho and c = beta rho^r rho^b/rho n.
 template <int D>
 struct InCompact {
   static constexpr bool kPull = true;
   const float* T;
-  const float* A;
-  const float* Cc;
+  const float4* AC;
   int Np;
   float rho0;
   template <int i, class CT>
   __device__ __forceinline__ void get(int s, CT& r, CT& x) const {
     constexpr double w = Lat<D>::w(i);
     const CT t = (CT)T[i * Np + s];
-    const CT a = (CT)A[s];
-    CT r0 = a * ((CT)w * (CT)rho0 + t);
+    const float4 ac = AC[s];
+    CT r0 = (CT)ac.x * ((CT)w * (CT)rho0 + t);
     if constexpr (i != 0) {
+      const CT cc[3] = {(CT)ac.y, (CT)ac.z, (CT)ac.w};
       CT ce = CT(0);
       unroll<D>([&](auto A_) {
         constexpr int d = A_;
         constexpr int e = Lat<D>::e(i, d);
-        if constexpr (e == 1) ce = ce + (CT)Cc[d * Np + s];
-        if constexpr (e == -1) ce = ce - (CT)Cc[d * Np + s];
+        if constexpr (e == 1) ce = ce + cc[d];
+        if constexpr (e == -1) ce = ce - cc[d];
       });
       r0 = r0 + (CT)w * ce;
     }
@@ -211,8 +229,7 @@ struct OutCanon {
 template <int D>
 struct OutCompact {
   float* T;
-  float* A;
-  float* Cc;
+  float4* AC;
   int Np;
 };
 
@@ -565,6 +582,62 @@ __device__ __forceinline__ void collide_mrt(CT* ft, CT drho, CT rho0, const CT* 
       }
     });
     ft[i] = ft[i] - s;
+  });
+}
+
+// MRT collision, single-precision form: with y = f - f^eq + Fbar/2 the same
+// operator reads f'' = f + Fbar - M^-1 S M y (S vanishes on the conserved
+// moments), so only the 15 non-conserved moments of y are accumulated, one
+// population at a time, and no per-moment temporaries are kept.
+template <class CT>
+__device__ __forceinline__ void collide_mrt_fast(CT* g, CT drho, CT rho0, const CT* u, const CT* F, CT s_nu,
+                                                 CT s_q) {
+  constexpr int D = 3;
+  CT usq = u[0] * u[0];
+  usq = usq + u[1] * u[1];
+  usq = usq + u[2] * u[2];
+  CT m[19];
+  unroll<19>([&](auto K) {
+    constexpr int k = K;
+    if constexpr (rate_class(k) != 0) m[k] = CT(0);
+  });
+  unroll<19>([&](auto I) {
+    constexpr int i = I;
+    const CT y = g[i] - eq_i<D, i>(drho, rho0, u, usq) + CT(0.5) * guo_i<D, i>(u, F);
+    unroll<19>([&](auto K) {
+      constexpr int k = K;
+      constexpr int mk = Mkj(k, i);
+      if constexpr (rate_class(k) != 0 && mk != 0) {
+        if constexpr (mk == 1)
+          m[k] = m[k] + y;
+        else if constexpr (mk == -1)
+          m[k] = m[k] - y;
+        else
+          m[k] = m[k] + (CT)mk * y;
+      }
+    });
+  });
+  unroll<19>([&](auto K) {
+    constexpr int k = K;
+    constexpr int rc = rate_class(k);
+    if constexpr (rc != 0) m[k] = m[k] * ((rc == 1 ? s_nu : s_q) * (CT)(1.0 / (double)Mnorm2(k)));
+  });
+  unroll<19>([&](auto I) {
+    constexpr int i = I;
+    CT s = guo_i<D, i>(u, F);
+    unroll<19>([&](auto K) {
+      constexpr int k = K;
+      constexpr int mk = Mkj(k, i);
+      if constexpr (rate_class(k) != 0 && mk != 0) {
+        if constexpr (mk == 1)
+          s = s - m[k];
+        else if constexpr (mk == -1)
+          s = s + m[k];
+        else
+          s = s - (CT)mk * m[k];
+      }
+    });
+    g[i] = g[i] + s;
   });
 }
 

@@ -172,7 +172,7 @@ class Sim:
         L.check(L.load().cg_lbm_load(self._h, buf.ctypes.data_as(C.c_void_p)))
 
     # ---------------------------------------------------------------- timing
-    KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_main")
+    KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main")
 
     def set_timing(self, kernels="all"):
         """Bracket launches of the named kernels with HIP events ("all", None,
