@@ -85,6 +85,66 @@ def cpu_baseline(case, kw, budget_s=20.0):
                        f"{el:.1f} s, OpenMP threads={threads}")
 
 
+def batched_leg(steps, warmup, count=64, ref_edge=256):
+    """64 sessile-drop runs (edges drawn from {48, 64, 96, 128}, contact angles
+    uniform in 15-165 deg, Scheme-I for even and Scheme-II for odd runs, FP32
+    MRT) advanced by the batched persistent launches, against one large run of
+    the same setup (edge 256, 90 deg)."""
+    import torch
+
+    from paper_2407_10914_amd import inputs
+    from paper_2407_10914_amd.sim import Batch, Sim
+
+    edges = inputs.sweep_edges(count)
+    thetas = inputs.contact_angles(count)
+
+    def make(edge, theta, scheme):
+        c = inputs.sessile_3d(edge=edge)
+        s = Sim(c.solid, dim=3, periodic=c.periodic, tau_r=1.0, tau_b=1.0, sigma=1.0 / 45.0, beta=0.95,
+                scheme=scheme, theta_deg=theta, collision=1, precision="f32")
+        s.set_phase(c.phi0)
+        return s
+
+    t0 = time.perf_counter()
+    sims = [make(edges[k], thetas[k], 1 if k % 2 == 0 else 2) for k in range(count)]
+    batch = Batch(sims)
+    voxels = sum(e ** 3 for e in edges)
+    report = batch.tune(reps=3)
+    print(f"# batch setup+tune {time.perf_counter() - t0:.1f} s: {report}", file=sys.stderr, flush=True)
+    batch.step(warmup)
+    batch.sync()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    batch.step(steps)
+    e1.record(stream)
+    batch.sync()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nodes = batch.info()["total_nodes"]
+    batched = nodes * steps / (ms / 1e3) / 1e6
+    del batch
+    del sims
+    torch.cuda.empty_cache()
+    # the single large run of the same setup
+    big = make(ref_edge, 90.0, 1)
+    big.step(warmup)
+    big.sync()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    big.step(steps)
+    e1.record(stream)
+    big.sync()
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    single = big.info()["fluid"] * steps / (ms1 / 1e3) / 1e6
+    del big
+    torch.cuda.empty_cache()
+    return {"runs": count, "voxels": int(voxels), "fluid_nodes": int(nodes), "steps": steps,
+            "batched_mlups": round(batched, 1), "single_256_sessile_mlups": round(single, 1),
+            "ratio": round(batched / single, 4), "tuning": report}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -155,11 +217,14 @@ def main():
         torch.cuda.synchronize()
         print("# copy calibration: 3 x 1 GiB device-to-device copies", file=sys.stderr, flush=True)
         del x, y
+    batched = None
+    if not args.no_batch:
+        batched = batched_leg(args.batch_steps, max(2, args.warmup // 4))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(case, kw)
     line = {
-        "metric": "MLUPS D3Q19 color-gradient 256^3",
+        "metric": "MLUPS D3Q19 color-gradient 256^3; batched MLUPS; adjoint/forward time ratio",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -175,7 +240,7 @@ def main():
                                "porosity 0.22, Zou-He drho=0.02, Scheme-I 30 deg, MRT, FP32",
                    "fluid_nodes": n_fluid, "voxels": info["voxels"], "voxel_mlups": round(vox_mlups, 1),
                    "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3),
-                   "sat_nw_mass": obs["sat_nw_mass"]},
+                   "sat_nw_mass": obs["sat_nw_mass"], "batched": batched},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

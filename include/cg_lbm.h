@@ -228,6 +228,37 @@ cg_status cg_lbm_set_timing(cg_lbm* h, int mask);
 cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n);
 cg_status cg_lbm_reset_timing(cg_lbm* h);
 
+/* ---------------------------------------------------------------------- */
+/* Batched runs.  Many runs of one precision, one lattice and one stream
+ * advance together: each stage of the step is one persistent launch over a
+ * table of (run, tile) pairs for all runs, and the step loop is replayed from
+ * a captured hipGraph.  The batch references the runs' device state and does
+ * not own the runs: they must outlive it.  A run of a batch can still be
+ * observed, read or stepped on its own through its cg_lbm handle (call
+ * cg_batch_sync first); its step counter and buffers stay consistent. */
+typedef struct cg_batch cg_batch;
+
+/* runs: n >= 1 handles (caller-owned array, copied).  Errors: CG_EINVAL when
+ * precision, lattice or stream differ. */
+cg_status cg_batch_create(cg_lbm* const* runs, int n, cg_batch** out);
+void cg_batch_destroy(cg_batch* b);
+/* Enqueue n steps of every run (asynchronous). */
+cg_status cg_batch_step(cg_batch* b, int64_t n);
+cg_status cg_batch_sync(cg_batch* b);
+/* on = 0: enqueue the stage launches directly instead of replaying a graph. */
+cg_status cg_batch_set_graph(cg_batch* b, int on);
+/* Autotuner: for every stage, time each block size in {64, 128, 256} and
+ * persistent grid size in {one block per tile, 4, 8, 16, 32 blocks per CU}
+ * over reps launches on the batch's own data, keep the fastest, and cache the
+ * choice in $CGLBM_TUNE_CACHE (default ~/.cache/cglbm_autotune.txt) keyed by
+ * architecture, lattice, precision and batch size class.  Takes one step
+ * first when a run's state was just set.  report (may be NULL) receives a
+ * summary. */
+cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len);
+/* total fluid nodes; chosen block and grid per stage (6 entries each, stages
+ * in step order; grid 0 = one block per tile) */
+cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid);
+
 #ifdef __cplusplus
 }
 #endif

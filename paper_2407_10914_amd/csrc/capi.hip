@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/cg_lbm.h"
+#include "batch_base.hpp"
 #include "engine_base.hpp"
 #include "setup.hpp"
 
@@ -329,6 +330,85 @@ cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, dou
 cg_status cg_lbm_reset_timing(cg_lbm* h) {
   if (!h) return fail(CG_EINVAL, "NULL handle");
   h->eng->reset_timing();
+  return CG_OK;
+}
+
+struct cg_batch {
+  std::unique_ptr<cg::BatchBase> impl;
+  std::vector<cg_lbm*> runs;
+};
+
+cg_status cg_batch_create(cg_lbm* const* runs, int n, cg_batch** out) {
+  if (!out) return fail(CG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!runs || n < 1) return fail(CG_EINVAL, "need at least one run");
+  std::vector<cg::EngineBase*> engs;
+  for (int i = 0; i < n; ++i) {
+    if (!runs[i]) return fail(CG_EINVAL, "NULL run handle");
+    if (runs[i]->precision != runs[0]->precision) return fail(CG_EINVAL, "runs differ in precision");
+    engs.push_back(runs[i]->eng.get());
+  }
+  std::unique_ptr<cg_batch> b(new cg_batch());
+  b->runs.assign(runs, runs + n);
+  b->impl.reset(runs[0]->precision == CG_FP64 ? cg::make_batch_f64() : cg::make_batch_f32());
+  std::string err;
+  int rc = b->impl->init(engs, &runs[0]->al, &err);
+  if (rc != CG_OK) return fail((cg_status)rc, err.empty() ? b->impl->err_ : err);
+  *out = b.release();
+  return CG_OK;
+}
+
+void cg_batch_destroy(cg_batch* b) {
+  if (!b) return;
+  (void)b->impl->sync();
+  delete b;
+}
+
+cg_status cg_batch_step(cg_batch* b, int64_t n) {
+  if (!b || n < 0) return fail(CG_EINVAL, "bad argument");
+  int rc = b->impl->step(n);
+  return rc == CG_OK ? CG_OK : fail((cg_status)rc, b->impl->err_);
+}
+
+cg_status cg_batch_sync(cg_batch* b) {
+  if (!b) return fail(CG_EINVAL, "NULL batch");
+  int rc = b->impl->sync();
+  return rc == CG_OK ? CG_OK : fail((cg_status)rc, b->impl->err_);
+}
+
+cg_status cg_batch_set_graph(cg_batch* b, int on) {
+  if (!b) return fail(CG_EINVAL, "NULL batch");
+  b->impl->set_graph(on != 0);
+  return CG_OK;
+}
+
+cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len) {
+  if (!b || reps < 1) return fail(CG_EINVAL, "bad argument");
+  bool any_pre = false;
+  for (cg_lbm* r : b->runs) any_pre = any_pre || cg_lbm_time(r) == 0;
+  if (any_pre) {
+    int rc = b->impl->step(1);
+    if (rc != CG_OK) return fail((cg_status)rc, b->impl->err_);
+  }
+  std::string rep;
+  int rc = b->impl->tune(reps, &rep);
+  if (rc != CG_OK) return fail((cg_status)rc, b->impl->err_);
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return CG_OK;
+}
+
+cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid) {
+  if (!b) return fail(CG_EINVAL, "NULL batch");
+  if (total_nodes) *total_nodes = b->impl->total_nodes();
+  int bs[6], gr[6];
+  b->impl->get_config(bs, gr);
+  for (int k = 0; k < 6; ++k) {
+    if (block) block[k] = bs[k];
+    if (grid) grid[k] = gr[k];
+  }
   return CG_OK;
 }
 

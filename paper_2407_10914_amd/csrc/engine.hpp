@@ -305,6 +305,36 @@ class Engine final : public EngineBase {
   size_t state_bytes() const override { return state_bytes_; }
   size_t device_bytes() const override { return al_ ? al_->total : dev_bytes_; }
 
+  // ---- access for the batch engine (same precision, same translation unit)
+  const StepParams& params() const { return P_; }
+  const Geo<Real>& geo() const { return G_; }
+  const Grids<Real>& grids() const { return R_; }
+  int dim() const { return dim_; }
+  int cur() const { return cur_; }
+  bool pre() const { return pre_; }
+  hipStream_t stream() const { return stream_; }
+  // post-collision state held in buffer c, and the writer into buffer c ^ 1
+  template <int D>
+  auto in_at(int c) const {
+    if constexpr (kF32)
+      return InCompact<D>{T_[c], AC_[c], P_.Np, (float)P_.rho0};
+    else
+      return InCanon<Real, D>{fr_[c], fb_[c], P_.Np};
+  }
+  template <int D>
+  auto out_at(int c) const {
+    if constexpr (kF32)
+      return OutCompact<D>{T_[c ^ 1], AC_[c ^ 1], P_.Np};
+    else
+      return OutCanon<Real, D>{fr_[c ^ 1], fb_[c ^ 1], P_.Np};
+  }
+  // account for n steps taken by a batch launch
+  void advance(int64_t n) {
+    if (n & 1) cur_ ^= 1;
+    t += n;
+    if (n) pre_ = false;
+  }
+
  private:
   StepParams P_{};
   Geo<Real> G_{};

@@ -18,11 +18,10 @@ __device__ __forceinline__ unsigned flags_of(unsigned vf) { return vf >> kVoxBit
 // phi_in (Sec. II.D.1), outlet nodes the phase one node upstream (Eq. 39).
 // The sums are taken in double for either state layout.
 template <class Real, int D, class In>
-__global__ void k_phase(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
+__device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, const In& in, int n) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = double;
-  const int n = node_id();
   if (n >= P.N) return;
   const unsigned vf = G.vf[n];
   const unsigned fl = flags_of(vf);
@@ -53,12 +52,16 @@ __global__ void k_phase(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
   R.phi[vox_of(vf)] = (Real)phi;
 }
 
+template <class Real, int D, class In>
+__global__ void k_phase(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
+  d_phase<Real, D, In>(P, G, R, in, node_id());
+}
+
 // ----------------------------------------------------------------- k_sb_phi
 // Eq. (34): weighted mean of the fluid link neighbours, i ascending.
 template <class Real, int D>
-__global__ void k_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R) {
+__device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int s) {
   constexpr int Q = Lat<D>::Q;
-  const int s = node_id();
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
@@ -76,15 +79,19 @@ __global__ void k_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R) {
   R.phi[v] = num / den;
 }
 
+template <class Real, int D>
+__global__ void k_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R) {
+  d_sb_phi<Real, D>(P, G, R, node_id());
+}
+
 // ----------------------------------------------------------------- k_normal
 // Colour gradient, Eq. (6), unit normal, Eq. (27), wetting at the fluid
 // boundary points (Sec. II.B.3 step 3) keeping |C|.  Double arithmetic for
 // either layout.
 template <class Real, int D>
-__global__ void k_normal(StepParams P, Geo<Real> G, Grids<Real> R) {
+__device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int n) {
   constexpr int Q = Lat<D>::Q;
   using CT = double;
-  const int n = node_id();
   if (n >= P.N) return;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
@@ -142,12 +149,16 @@ __global__ void k_normal(StepParams P, Geo<Real> G, Grids<Real> R) {
   R.c[n] = cv;
 }
 
+template <class Real, int D>
+__global__ void k_normal(StepParams P, Geo<Real> G, Grids<Real> R) {
+  d_normal<Real, D>(P, G, R, node_id());
+}
+
 // ------------------------------------------------------------------- k_sb_n
 // Eq. (35): normal extrapolated to the solid boundary points, not renormalised.
 template <class Real, int D>
-__global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
+__device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int s) {
   constexpr int Q = Lat<D>::Q;
-  const int s = node_id();
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
@@ -173,14 +184,18 @@ __global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
   R.n[v] = o;
 }
 
+template <class Real, int D>
+__global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
+  d_sb_n<Real, D>(P, G, R, node_id());
+}
+
 // ------------------------------------------------------------------- k_curv
 // Curvature, Eq. (12), from the isotropic derivatives of n (same stencil as
 // Eq. 6), and the force F = 1/2 sigma kappa C (Eq. 5) + rho_o g (Eq. 36).
 template <class Real, int D>
-__global__ void k_curv(StepParams P, Geo<Real> G, Grids<Real> R) {
+__device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int n) {
   constexpr int Q = Lat<D>::Q;
   using CT = double;
-  const int n = node_id();
   if (n >= P.N) return;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
@@ -233,6 +248,11 @@ __global__ void k_curv(StepParams P, Geo<Real> G, Grids<Real> R) {
   R.f[n] = o;
 }
 
+template <class Real, int D>
+__global__ void k_curv(StepParams P, Geo<Real> G, Grids<Real> R) {
+  d_curv<Real, D>(P, G, R, node_id());
+}
+
 // ------------------------------------------------------------------- k_main
 enum { MODE_STEP = 0, MODE_MACRO = 1, MODE_OBS = 2 };
 
@@ -283,171 +303,175 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // Pull, faces, velocity, rates, collision, recolouring, store (MODE_STEP);
 // or the macroscopic fields (MODE_MACRO); or the observable reductions
 // (MODE_OBS).
-template <class Real, int D, int BS, int Mode, class In, class Out>
-__global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Real> R, In in, Out out,
-                                             MacroOut mo, ObsOut oo) {
+// Per-node part of the fused kernel (n < P.N).  MODE_OBS accumulates into o.
+template <class Real, int D, int Mode, class In, class Out>
+__device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, const In& in,
+                                       const Out& out, const MacroOut& mo, int n, double* o) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = double;
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const unsigned fl = flags_of(vf);
+  Real fr[Q], fx[Q];
+  load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+  if constexpr (In::kPull) {
+    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
+  }
+  Real rr, rb, rho, drho;
+  node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
+  const Real phi = R.phi[v];
+  const Vec4<Real> f4 = R.f[n];
+  const Vec4<Real> n4 = R.n[v];
+  // velocity, Eq. (22), in the storage precision for the collision and in
+  // double for the reported fields; the deviation layout balances momentum
+  // with rho0 + sum g
+  using UT = std::conditional_t<Mode == MODE_STEP, Real, CT>;
+  const UT F[3] = {(UT)f4.x, (UT)f4.y, (UT)f4.z};
+  const UT rho_u = kDev ? (UT)P.rho0 + (UT)drho : (UT)rho;
+  UT u[3] = {UT(0), UT(0), UT(0)};
+  unroll<D>([&](auto A_) {
+    constexpr int a = A_;
+    UT j = UT(0);
+    bool first = true;
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int e = Lat<D>::e(i, a);
+      if constexpr (e != 0) {
+        const UT t = e == 1 ? (UT)fx[i] : -(UT)fx[i];
+        j = first ? t : j + t;
+        first = false;
+      }
+    });
+    u[a] = (j + UT(0.5) * F[a]) / rho_u;
+  });
+  if constexpr (Mode == MODE_STEP) {
+    Real s_nu, s_q;
+    rates(P, phi, s_nu, s_q);
+    Real ur[3], Fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ur[a] = (Real)u[a];
+      Fr[a] = (Real)F[a];
+    }
+    if constexpr (D == 3) {
+      if (P.collision == 1) {
+        if constexpr (kDev)
+          collide_mrt_fast(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
+        else
+          collide_mrt<true>(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
+      } else
+        collide_bgk<D>(fx, drho, (Real)P.rho0, ur, Fr, s_nu);
+    } else {
+      collide_bgk<D>(fx, drho, (Real)P.rho0, ur, Fr, s_nu);
+    }
+    // recolouring, Eqs. (20)-(21)
+    const Real rsum = rr + rb;
+    const Real a = rr / rsum;
+    const Real b = rr * rb / rsum;
+    if constexpr (kDev) {
+      const Real bb = (Real)P.beta * b;
+      float4 ac;
+      ac.x = a;
+      ac.y = bb * n4.x;
+      ac.z = bb * n4.y;
+      ac.w = D == 3 ? bb * n4.z : 0.f;
+      out.AC[n] = ac;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out.T[i * out.Np + n] = fx[i];
+    } else {
+      const Real nvec[3] = {n4.x, n4.y, n4.z};
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        const Real fpp = fx[i];
+        Real r;
+        if constexpr (i == 0) {
+          r = a * fpp;
+        } else {
+          Real edn = Real(0);
+          bool first = true;
+          unroll<D>([&](auto C_) {
+            constexpr int c = C_;
+            constexpr int e = Lat<D>::e(i, c);
+            if constexpr (e != 0) {
+              const Real t = e == 1 ? nvec[c] : -nvec[c];
+              edn = first ? t : edn + t;
+              first = false;
+            }
+          });
+          constexpr double w = Lat<D>::w(i);
+          r = a * fpp + (Real)P.beta * (Real)w * b * edn;
+        }
+        out.fr[i * out.Np + n] = r;
+        out.fb[i * out.Np + n] = fpp - r;
+      });
+    }
+  } else if constexpr (Mode == MODE_MACRO) {
+    const Vec4<Real> c4 = R.c[n];
+    if (mo.rho_r) mo.rho_r[v] = (double)rr;
+    if (mo.rho_b) mo.rho_b[v] = (double)rb;
+    if (mo.phi) mo.phi[v] = (double)phi;
+    if (mo.kappa) mo.kappa[v] = (double)f4.w;
+    const double cc[3] = {(double)c4.x, (double)c4.y, (double)c4.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (mo.u) mo.u[(size_t)a * P.V + v] = (double)u[a];
+      if (mo.force) mo.force[(size_t)a * P.V + v] = (double)F[a];
+      if (mo.cvec) mo.cvec[(size_t)a * P.V + v] = cc[a];
+    }
+  } else {
+    const double a = rr, b = rb, ph = phi;
+    double u2 = 0.0;
+    bool ok = isfinite(a) && isfinite(b);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      ok = ok && isfinite((double)u[c]);
+      u2 += (double)u[c] * (double)u[c];
+    }
+    if (!ok) {
+      o[11] = 1.0;
+    } else {
+      o[0] = a;
+      o[1] = b;
+      o[2] = 1.0;
+      o[3] = ph < 0.0 ? 1.0 : 0.0;
+      o[4] = (1.0 + ph) / 2.0;
+      o[5] = (1.0 - ph) / 2.0;
+      const double pr = (a + b) / 3.0;
+      if (ph > 0.9) {
+        o[6] = pr;
+        o[7] = 1.0;
+      }
+      if (ph < -0.9) {
+        o[8] = pr;
+        o[9] = 1.0;
+      }
+      o[10] = sqrt(u2);
+      if (P.flux_axis >= 0 && P.flux_axis < D) {
+        const int nxy = P.nx * P.ny;
+        const int z = v / nxy, r = v - z * nxy, y = r / P.nx, x = r - y * P.nx;
+        const int c = P.flux_axis == 0 ? x : (P.flux_axis == 1 ? y : z);
+        if (c == P.flux_plane) {
+          const double ua = (double)u[P.flux_axis];
+          o[12] = (a + b) * ua;
+          o[13] = a * ua;
+          o[14] = b * ua;
+        }
+      }
+    }
+  }
+}
+
+template <class Real, int D, int BS, int Mode, class In, class Out>
+__global__ void __launch_bounds__(BS) k_main(StepParams P, Geo<Real> G, Grids<Real> R, In in, Out out,
+                                             MacroOut mo, ObsOut oo) {
   const int n = node_id();
-  const bool active = n < P.N;
   double o[kObsN];
   if constexpr (Mode == MODE_OBS) {
 #pragma unroll
     for (int k = 0; k < kObsN; ++k) o[k] = 0.0;
   }
-  if (active) {
-    const unsigned vf = G.vf[n];
-    const int v = vox_of(vf);
-    const unsigned fl = flags_of(vf);
-    Real fr[Q], fx[Q];
-    load_node<D>(in, G.nbr, P.Np, n, fr, fx);
-    if constexpr (In::kPull) {
-      if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
-    }
-    Real rr, rb, rho, drho;
-    node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
-    const Real phi = R.phi[v];
-    const Vec4<Real> f4 = R.f[n];
-    const Vec4<Real> n4 = R.n[v];
-    // velocity, Eq. (22), in the storage precision for the collision and in
-    // double for the reported fields; the deviation layout balances momentum
-    // with rho0 + sum g
-    using UT = std::conditional_t<Mode == MODE_STEP, Real, CT>;
-    const UT F[3] = {(UT)f4.x, (UT)f4.y, (UT)f4.z};
-    const UT rho_u = kDev ? (UT)P.rho0 + (UT)drho : (UT)rho;
-    UT u[3] = {UT(0), UT(0), UT(0)};
-    unroll<D>([&](auto A_) {
-      constexpr int a = A_;
-      UT j = UT(0);
-      bool first = true;
-      unroll<Q>([&](auto I) {
-        constexpr int i = I;
-        constexpr int e = Lat<D>::e(i, a);
-        if constexpr (e != 0) {
-          const UT t = e == 1 ? (UT)fx[i] : -(UT)fx[i];
-          j = first ? t : j + t;
-          first = false;
-        }
-      });
-      u[a] = (j + UT(0.5) * F[a]) / rho_u;
-    });
-    if constexpr (Mode == MODE_STEP) {
-      Real s_nu, s_q;
-      rates(P, phi, s_nu, s_q);
-      Real ur[3], Fr[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        ur[a] = (Real)u[a];
-        Fr[a] = (Real)F[a];
-      }
-      if constexpr (D == 3) {
-        if (P.collision == 1) {
-          if constexpr (kDev)
-            collide_mrt_fast(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
-          else
-            collide_mrt<true>(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
-        } else
-          collide_bgk<D>(fx, drho, (Real)P.rho0, ur, Fr, s_nu);
-      } else {
-        collide_bgk<D>(fx, drho, (Real)P.rho0, ur, Fr, s_nu);
-      }
-      // recolouring, Eqs. (20)-(21)
-      const Real rsum = rr + rb;
-      const Real a = rr / rsum;
-      const Real b = rr * rb / rsum;
-      if constexpr (kDev) {
-        const Real bb = (Real)P.beta * b;
-        float4 ac;
-        ac.x = a;
-        ac.y = bb * n4.x;
-        ac.z = bb * n4.y;
-        ac.w = D == 3 ? bb * n4.z : 0.f;
-        out.AC[n] = ac;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) out.T[i * out.Np + n] = fx[i];
-      } else {
-        const Real nvec[3] = {n4.x, n4.y, n4.z};
-        unroll<Q>([&](auto I) {
-          constexpr int i = I;
-          const Real fpp = fx[i];
-          Real r;
-          if constexpr (i == 0) {
-            r = a * fpp;
-          } else {
-            Real edn = Real(0);
-            bool first = true;
-            unroll<D>([&](auto C_) {
-              constexpr int c = C_;
-              constexpr int e = Lat<D>::e(i, c);
-              if constexpr (e != 0) {
-                const Real t = e == 1 ? nvec[c] : -nvec[c];
-                edn = first ? t : edn + t;
-                first = false;
-              }
-            });
-            constexpr double w = Lat<D>::w(i);
-            r = a * fpp + (Real)P.beta * (Real)w * b * edn;
-          }
-          out.fr[i * out.Np + n] = r;
-          out.fb[i * out.Np + n] = fpp - r;
-        });
-      }
-    } else if constexpr (Mode == MODE_MACRO) {
-      const Vec4<Real> c4 = R.c[n];
-      if (mo.rho_r) mo.rho_r[v] = (double)rr;
-      if (mo.rho_b) mo.rho_b[v] = (double)rb;
-      if (mo.phi) mo.phi[v] = (double)phi;
-      if (mo.kappa) mo.kappa[v] = (double)f4.w;
-      const double cc[3] = {(double)c4.x, (double)c4.y, (double)c4.z};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (mo.u) mo.u[(size_t)a * P.V + v] = (double)u[a];
-        if (mo.force) mo.force[(size_t)a * P.V + v] = (double)F[a];
-        if (mo.cvec) mo.cvec[(size_t)a * P.V + v] = cc[a];
-      }
-    } else {
-      const double a = rr, b = rb, ph = phi;
-      double u2 = 0.0;
-      bool ok = isfinite(a) && isfinite(b);
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        ok = ok && isfinite((double)u[c]);
-        u2 += (double)u[c] * (double)u[c];
-      }
-      if (!ok) {
-        o[11] = 1.0;
-      } else {
-        o[0] = a;
-        o[1] = b;
-        o[2] = 1.0;
-        o[3] = ph < 0.0 ? 1.0 : 0.0;
-        o[4] = (1.0 + ph) / 2.0;
-        o[5] = (1.0 - ph) / 2.0;
-        const double pr = (a + b) / 3.0;
-        if (ph > 0.9) {
-          o[6] = pr;
-          o[7] = 1.0;
-        }
-        if (ph < -0.9) {
-          o[8] = pr;
-          o[9] = 1.0;
-        }
-        o[10] = sqrt(u2);
-        if (P.flux_axis >= 0 && P.flux_axis < D) {
-          const int nxy = P.nx * P.ny;
-          const int z = v / nxy, r = v - z * nxy, y = r / P.nx, x = r - y * P.nx;
-          const int c = P.flux_axis == 0 ? x : (P.flux_axis == 1 ? y : z);
-          if (c == P.flux_plane) {
-            const double ua = (double)u[P.flux_axis];
-            o[12] = (a + b) * ua;
-            o[13] = a * ua;
-            o[14] = b * ua;
-          }
-        }
-      }
-    }
-  }
+  if (n < P.N) d_main<Real, D, Mode>(P, G, R, in, out, mo, n, o);
   if constexpr (Mode == MODE_OBS) {
     __shared__ double sh[BS / 64];
 #pragma unroll

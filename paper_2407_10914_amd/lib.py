@@ -26,7 +26,9 @@ FIELDS = {"rho_r": (0, 1), "rho_b": (1, 1), "phi": (2, 1), "u": (3, 3), "f_r": (
 EXPORTS = ("cg_options_default", "cg_lbm_create", "cg_lbm_destroy", "cg_last_error", "cg_lbm_set_phase",
            "cg_lbm_set_state", "cg_lbm_step", "cg_lbm_sync", "cg_lbm_time", "cg_lbm_observe",
            "cg_lbm_get_field", "cg_lbm_info", "cg_lbm_snapshot_bytes", "cg_lbm_save", "cg_lbm_load",
-           "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing")
+           "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing", "cg_batch_create",
+           "cg_batch_destroy", "cg_batch_step", "cg_batch_sync", "cg_batch_set_graph", "cg_batch_tune",
+           "cg_batch_info")
 
 
 class CgError(RuntimeError):
@@ -119,6 +121,14 @@ def load():
     L.cg_lbm_set_timing.argtypes = [p, i]
     L.cg_lbm_kernel_times.argtypes = [p, p, p, p, C.POINTER(C.c_int)]
     L.cg_lbm_reset_timing.argtypes = [p]
+    L.cg_batch_create.argtypes = [p, i, C.POINTER(p)]
+    L.cg_batch_destroy.argtypes = [p]
+    L.cg_batch_destroy.restype = None
+    L.cg_batch_step.argtypes = [p, i64]
+    L.cg_batch_sync.argtypes = [p]
+    L.cg_batch_set_graph.argtypes = [p, i]
+    L.cg_batch_tune.argtypes = [p, i, C.c_char_p, C.c_size_t]
+    L.cg_batch_info.argtypes = [p, C.POINTER(i64), p, p]
     _LIB = L
     return L
 

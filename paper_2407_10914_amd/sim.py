@@ -197,3 +197,50 @@ class Sim:
         n = C.c_int(16)
         L.check(L.load().cg_lbm_kernel_times(self._h, names, counts, ms, C.byref(n)))
         return {bytes(names[k]).split(b"\0", 1)[0].decode(): (counts[k], ms[k]) for k in range(n.value)}
+
+
+class Batch:
+    """Runs of one precision and lattice advanced together by persistent
+    launches (one per stage for all runs) replayed from a hipGraph.  The runs
+    (Sim objects) must outlive the batch; each can still be observed or read
+    through its own Sim after sync()."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        h = C.c_void_p()
+        L.check(L.load().cg_batch_create(arr, len(self.sims), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            L.load().cg_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        L.check(L.load().cg_batch_step(self._h, int(n)))
+
+    def sync(self):
+        L.check(L.load().cg_batch_sync(self._h))
+
+    def set_graph(self, on=True):
+        L.check(L.load().cg_batch_set_graph(self._h, 1 if on else 0))
+
+    def tune(self, reps=5):
+        buf = C.create_string_buffer(4096)
+        L.check(L.load().cg_batch_tune(self._h, int(reps), buf, 4096))
+        return buf.value.decode()
+
+    def info(self):
+        n = C.c_int64()
+        bs = (C.c_int * 6)()
+        gr = (C.c_int * 6)()
+        L.check(L.load().cg_batch_info(self._h, C.byref(n), bs, gr))
+        return {"total_nodes": n.value, "block": list(bs), "grid": list(gr)}

@@ -56,3 +56,10 @@ def rel(a, b, mask=None):
     den = np.linalg.norm(b.ravel())
     num = np.linalg.norm((a - b).ravel())
     return num / den if den > 0 else num
+
+
+def sessile_3d(edge, theta, scheme, sigma=1.0 / 45.0, beta=0.95):
+    c = inputs.sessile_3d(edge=edge)
+    kw = dict(dim=3, periodic=c.periodic, tau_r=1.0, tau_b=1.0, sigma=sigma, beta=beta, scheme=scheme,
+              theta_deg=theta, collision=1)
+    return c, kw

@@ -1,0 +1,104 @@
+"""Batched persistent launches: every run of a batch advances exactly as it
+does on its own (bitwise in double precision; in single precision to the
+rounding of the same arithmetic), with or without the captured graph, before
+and after autotuning."""
+import numpy as np
+import pytest
+
+from cases import c2_tube, rel, sessile_3d
+
+pytestmark = pytest.mark.gpu
+
+
+def _runs(precision, specs):
+    from paper_2407_10914_amd.sim import Sim
+
+    out = []
+    for case, kw in specs:
+        s = Sim(case.solid, precision=precision, **kw)
+        s.set_phase(case.phi0)
+        out.append((case, s))
+    return out
+
+
+def _specs():
+    # uneven sizes, both schemes, angles on both sides of 90 degrees, and one
+    # run with Zou-He faces
+    return [sessile_3d(16, 40.0, 1), sessile_3d(20, 120.0, 2), sessile_3d(13, 75.0, 2),
+            c2_tube(scheme=1, theta=45.0, drive="type1", nz=24, radius=6.0, wet_len=8)]
+
+
+def _fields(s):
+    return [s.field("rho_r"), s.field("rho_b"), s.field("u")]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_matches_individual_runs(precision, graph):
+    from paper_2407_10914_amd.sim import Batch
+
+    specs = _specs()
+    solo = _runs(precision, specs)
+    batched = _runs(precision, specs)
+    b = Batch([s for _, s in batched])
+    b.set_graph(graph)
+    for n in (1, 6, 5):  # first step from the host state, then even and odd counts
+        b.step(n)
+        for _, s in solo:
+            s.step(n)
+    b.sync()
+    for (case, s1), (_, s2) in zip(solo, batched):
+        assert s1.time == s2.time == 12
+        fluid = case.solid == 0
+        for a, c in zip(_fields(s1), _fields(s2)):
+            r = rel(c, a, fluid)
+            if precision == "f64":
+                assert r == 0.0, r
+            else:
+                assert r <= 1e-6, r
+
+
+def test_batch_autotune_keeps_results(tmp_path, monkeypatch):
+    from paper_2407_10914_amd.sim import Batch
+
+    monkeypatch.setenv("CGLBM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    specs = _specs()
+    solo = _runs("f64", specs)
+    batched = _runs("f64", specs)
+    b = Batch([s for _, s in batched])
+    rep = b.tune(reps=2)
+    print(rep, flush=True)
+    info = b.info()
+    assert all(bs in (64, 128, 256) for bs in info["block"])
+    assert (tmp_path / "tune.txt").exists()
+    b.step(9)  # tune took the first step
+    for _, s in solo:
+        s.step(10)
+    b.sync()
+    for (case, s1), (_, s2) in zip(solo, batched):
+        fluid = case.solid == 0
+        for a, c in zip(_fields(s1), _fields(s2)):
+            assert rel(c, a, fluid) == 0.0
+    # a second batch over the same class reads the cached choice
+    b2 = Batch([s for _, s in batched])
+    assert b2.info()["block"] == info["block"] and b2.info()["grid"] == info["grid"]
+
+
+def test_run_stepped_alone_between_batch_steps():
+    from paper_2407_10914_amd.sim import Batch
+
+    specs = _specs()[:2]
+    solo = _runs("f64", specs)
+    batched = _runs("f64", specs)
+    b = Batch([s for _, s in batched])
+    b.step(4)
+    batched[0][1].step(3)  # one run advances on its own
+    b.step(4)
+    b.sync()
+    solo[0][1].step(11)
+    solo[1][1].step(8)
+    for (case, s1), (_, s2) in zip(solo, batched):
+        assert s1.time == s2.time
+        fluid = case.solid == 0
+        for a, c in zip(_fields(s1), _fields(s2)):
+            assert rel(c, a, fluid) == 0.0
