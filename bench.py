@@ -39,12 +39,15 @@ def workload(n=256):
     return case, kw
 
 
+# the sources that define the step kernels (k_main and the stages before it)
+STEP_SOURCES = ("lattice.hpp", "step.hpp", "kernels.hpp", "kernels_f32.hip")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2407_10914_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".hip", ".cpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -914,6 +914,22 @@ struct Sim {
     }
   }
 
+  /* Objectives of the adjoint checks, from the current state:
+   * 0: sum rho^r / sum rho over fluid nodes; 1: sum (1 + phi)/2. */
+  R objective(int which) {
+    R sr = 0.0, st = 0.0, vr = 0.0;
+    for (long v = 0; v < V; ++v) {
+      if (!fluid(v)) continue;
+      R a = 0.0, b = 0.0;
+      for (int i = 0; i < Q; ++i) a += fr[(size_t)i * V + v];
+      for (int i = 0; i < Q; ++i) b += fb[(size_t)i * V + v];
+      sr += a;
+      st += a + b;
+      vr += (1.0 + (a - b) / (a + b)) / 2.0;
+    }
+    return which == 0 ? sr / st : vr;
+  }
+
   void observe(int axis, int plane, orc_obs* o) {
     macro();
     std::memset(o, 0, sizeof(*o));
@@ -1085,6 +1101,38 @@ int orc_setup_info(const orc_sim* s, uint8_t* cls, double* g3, double* nw3, doub
     if (cos_t) cos_t[v] = m.cos_t[v];
     if (sin_t) sin_t[v] = m.sin_t[v];
   }
+  return 0;
+}
+
+int orc_objective(orc_sim* s, int objective, double* J) {
+  if (!s || !J) return fail("null argument");
+  *J = s->s.objective(objective);
+  return 0;
+}
+
+int orc_tangent(const orc_params* p, const uint8_t* solid, const double* theta_field_deg, const double* phi0,
+                const orc_tangent_spec* spec, double* J, double* dJ) {
+  if (!p || !solid || !phi0 || !spec || !J || !dJ) return fail("null argument");
+  Sim<Dual> m;
+  if (m.init(p, solid, theta_field_deg) != 0) return -1;
+  if (spec->seed == 0) {
+    if (theta_field_deg) return fail("seed 0 needs a global contact angle");
+    m.theta_global = Dual(p->theta_deg, 1.0);
+  } else if (spec->seed >= 1 && spec->seed <= 3) {
+    m.gforce[spec->seed - 1] = Dual(p->g[spec->seed - 1], 1.0);
+  } else if (spec->seed == 4) {
+    if (!theta_field_deg || !spec->theta_dir) return fail("seed 4 needs a theta field and a direction");
+    m.theta_vox_r.assign(m.V, 0.0);
+    for (long v = 0; v < m.V; ++v) m.theta_vox_r[v] = Dual(theta_field_deg[v], spec->theta_dir[v]);
+  } else {
+    return fail("unknown seed");
+  }
+  m.map_contact_angle();
+  m.set_phase(phi0);
+  for (int k = 0; k < spec->n_steps; ++k) m.step();
+  Dual j = m.objective(spec->objective);
+  *J = j.v;
+  *dJ = j.d;
   return 0;
 }
 

@@ -75,6 +75,25 @@ int orc_observe(orc_sim* s, int axis, int plane, orc_obs* out);
 int orc_setup_info(const orc_sim* s, uint8_t* cls, double* g3, double* nw3,
                    double* cos_t, double* sin_t);
 
+/* ---- discrete derivative of an objective (forward mode, dual numbers) ----
+ * Runs n_steps from the rest state of phi0 with every quantity carrying one
+ * directional derivative and returns J and dJ along the seeded parameter:
+ * seed 0: theta (global, degrees; requires no theta field), seed 1..3: the
+ * x/y/z component of the body-force acceleration g, seed 4: the per-voxel
+ * contact-angle field along theta_dir (V entries, degrees).
+ * objective 0: non-wetting mass saturation sum rho^r / sum rho;
+ * objective 1: red volume sum (1 + phi)/2 over fluid nodes. */
+typedef struct {
+  int objective;
+  int n_steps;
+  int seed;
+  const double* theta_dir;
+} orc_tangent_spec;
+int orc_tangent(const orc_params* p, const uint8_t* solid, const double* theta_field_deg, const double* phi0,
+                const orc_tangent_spec* spec, double* J, double* dJ);
+/* The objective of the current state of a plain run (same definitions). */
+int orc_objective(orc_sim* s, int objective, double* J);
+
 /* ---- single-node building blocks, exposed for the pin tests ---- */
 int orc_lattice(int dim, int* e /*[Q][3]*/, double* w, int* opp);
 int orc_mrt_matrix(double* M /*[19][19]*/, double* norm2 /*[19]*/);

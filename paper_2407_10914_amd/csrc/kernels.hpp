@@ -65,13 +65,13 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
-  const bool face = m & 1u;
+  const Pos ps = make_pos(P, v, m & 1u);
   Real num = Real(0), den = Real(0);
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     if (m & (1u << i)) {
       constexpr double w = Lat<D>::w(i);
-      const int y = nb_vox<D, i>(P, v, face);
+      const int y = nb_vox<D, i>(P, ps);
       num = num + (Real)w * R.phi[y];
       den = den + (Real)w;
     }
@@ -96,11 +96,11 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
-  const bool face = fl & FL_FACE;
+  const Pos ps = make_pos(P, v, fl & FL_FACE);
   Real ph[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
-    if constexpr (i > 0) ph[i] = R.phi[nb_vox<D, i>(P, v, face)];
+    if constexpr (i > 0) ph[i] = R.phi[nb_vox<D, i>(P, ps)];
   });
   CT C[3] = {CT(0), CT(0), CT(0)};
   unroll<D>([&](auto A_) {
@@ -162,14 +162,14 @@ __device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, 
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
-  const bool face = m & 1u;
+  const Pos ps = make_pos(P, v, m & 1u);
   Real num[3] = {Real(0), Real(0), Real(0)};
   Real den = Real(0);
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     if (m & (1u << i)) {
       constexpr double w = Lat<D>::w(i);
-      const Vec4<Real> q = R.n[nb_vox<D, i>(P, v, face)];
+      const Vec4<Real> q = R.n[nb_vox<D, i>(P, ps)];
       const Real qq[3] = {q.x, q.y, q.z};
 #pragma unroll
       for (int a = 0; a < D; ++a) num[a] = num[a] + (Real)w * qq[a];
@@ -199,11 +199,11 @@ __device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, 
   if (n >= P.N) return;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
-  const bool face = flags_of(vf) & FL_FACE;
+  const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
   Vec4<Real> nb[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
-    if constexpr (i > 0) nb[i] = R.n[nb_vox<D, i>(P, v, face)];
+    if constexpr (i > 0) nb[i] = R.n[nb_vox<D, i>(P, ps)];
   });
   const Vec4<Real> self = R.n[v];
   CT d[3][3];

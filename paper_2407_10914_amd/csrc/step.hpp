@@ -142,11 +142,43 @@ __device__ __forceinline__ int nb_slow(const StepParams& P, int v, int ex, int e
   return x + P.nx * (y + P.ny * z);
 }
 
+// A voxel and, when it lies on a domain face, its coordinates (decomposed once
+// per node rather than once per neighbour).
+struct Pos {
+  int v, x, y, z;
+  bool face;
+};
+
+__device__ __forceinline__ Pos make_pos(const StepParams& P, int v, bool face) {
+  Pos p{v, 0, 0, 0, face};
+  if (face) {
+    const int nxy = P.nx * P.ny;
+    p.z = v / nxy;
+    const int r = v - p.z * nxy;
+    p.y = r / P.nx;
+    p.x = r - p.y * P.nx;
+  }
+  return p;
+}
+
 template <int D, int i>
-__device__ __forceinline__ int nb_vox(const StepParams& P, int v, bool face) {
+__device__ __forceinline__ int nb_vox(const StepParams& P, const Pos& p) {
   constexpr int ex = Lat<D>::e(i, 0), ey = Lat<D>::e(i, 1), ez = Lat<D>::e(i, 2);
-  if (face) return nb_slow(P, v, ex, ey, ez);
-  return v + ex + P.nx * (ey + P.ny * ez);
+  if (!p.face) return p.v + ex + P.nx * (ey + P.ny * ez);
+  int x = p.x + ex, y = p.y + ey, z = p.z + ez;
+  if constexpr (ex != 0) {
+    if (x < 0) x = P.per[0] ? x + P.nx : 0;
+    if (x >= P.nx) x = P.per[0] ? x - P.nx : P.nx - 1;
+  }
+  if constexpr (ey != 0) {
+    if (y < 0) y = P.per[1] ? y + P.ny : 0;
+    if (y >= P.ny) y = P.per[1] ? y - P.ny : P.ny - 1;
+  }
+  if constexpr (ez != 0) {
+    if (z < 0) z = P.per[2] ? z + P.nz : 0;
+    if (z >= P.nz) z = P.per[2] ? z - P.nz : P.nz - 1;
+  }
+  return x + P.nx * (y + P.ny * z);
 }
 
 template <class Real, int D>
