@@ -37,6 +37,15 @@ class Obs(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class TangentSpec(C.Structure):
+    _fields_ = [("objective", C.c_int), ("axis", C.c_int), ("lo", C.c_int), ("hi", C.c_int), ("n_steps", C.c_int),
+                ("seed", C.c_int), ("theta_dir", C.c_void_p)]
+
+
+OBJECTIVES = {"sat_nw": 0, "red_volume": 1, "flux": 2}
+SEEDS = {"theta": 0, "gx": 1, "gy": 2, "gz": 3, "theta_field": 4}
+
+
 def lib():
     """Load liboracle.so, building it first if it is not there."""
     global _LIB
@@ -74,6 +83,8 @@ def lib():
         L.orc_scheme2.argtypes = [i, p, p, d, d, p]
         L.orc_zouhe_inlet.argtypes = [p, p, d, d]
         L.orc_zouhe_outlet.argtypes = [p, p, d, d]
+        L.orc_tangent.argtypes = [C.POINTER(Params), p, p, p, C.POINTER(TangentSpec), p, p]
+        L.orc_objective.argtypes = [p, i, i, i, i, p]
     return _LIB
 
 
@@ -201,6 +212,7 @@ class OracleSim:
         self.dim = dim
         self._solid = solid
         tf = None if theta_field is None else _f64(theta_field, solid.size)
+        self._theta_field = tf
         self._h = lib().orc_create(C.byref(P), _ptr(solid), _ptr(tf))
         if not self._h:
             raise ValueError("oracle: " + lib().orc_last_error().decode())
@@ -243,6 +255,29 @@ class OracleSim:
         n3, c3, f3 = (np.zeros((3,) + self.shape) for _ in range(3))
         _check(lib().orc_stages(self._h, _ptr(ph), _ptr(n3), _ptr(c3), _ptr(k), _ptr(f3)))
         return dict(phi=ph, n=n3, C=c3, kappa=k, F=f3)
+
+    def objective(self, which, axis=2, lo=0, hi=1 << 30):
+        """Objective of the current state (same definitions as ``tangent``)."""
+        J = C.c_double()
+        _check(lib().orc_objective(self._h, OBJECTIVES.get(which, which), axis, lo, hi, C.byref(J)))
+        return J.value
+
+    def tangent(self, phi0, *, objective, n_steps, seed, theta_dir=None, axis=2, lo=0, hi=1 << 30):
+        """(J, dJ) after n_steps from the rest state of phi0, dJ the exact
+        discrete directional derivative (forward mode, dual numbers) along the
+        seeded parameter: "theta" (global angle, per degree), "gx"/"gy"/"gz"
+        (body-force acceleration) or "theta_field" along theta_dir (dense
+        voxel array, degrees)."""
+        sp = TangentSpec()
+        sp.objective = OBJECTIVES.get(objective, objective)
+        sp.axis, sp.lo, sp.hi, sp.n_steps = axis, lo, hi, int(n_steps)
+        sp.seed = SEEDS.get(seed, seed)
+        td = None if theta_dir is None else _f64(theta_dir, self._solid.size)
+        sp.theta_dir = _ptr(td)
+        J, dJ = C.c_double(), C.c_double()
+        _check(lib().orc_tangent(C.byref(self.params), _ptr(self._solid), _ptr(self._theta_field),
+                                 _ptr(_f64(phi0, self._solid.size)), C.byref(sp), C.byref(J), C.byref(dJ)))
+        return J.value, dJ.value
 
     def observe(self, axis=2, plane=0):
         o = Obs()

@@ -914,12 +914,28 @@ struct Sim {
     }
   }
 
-  /* Objectives of the adjoint checks, from the current state:
-   * 0: sum rho^r / sum rho over fluid nodes; 1: sum (1 + phi)/2. */
-  R objective(int which) {
+  /* Objectives of the adjoint checks, from the current state, over the
+   * fluid nodes with lo <= coordinate[axis] < hi: 0: sum rho^r / sum rho;
+   * 1: sum (1 + phi)/2; 2: sum of rho u_axis over the plane coordinate == lo. */
+  R objective(int which, int axis, long lo, long hi) {
+    if (which == 2) {
+      macro();
+      R q = 0.0;
+      for (long v = 0; v < V; ++v) {
+        if (!fluid(v)) continue;
+        long c[3];
+        coords(v, c);
+        if (c[axis] != lo) continue;
+        q += rho[v] * uvel[axis * V + v];
+      }
+      return q;
+    }
     R sr = 0.0, st = 0.0, vr = 0.0;
     for (long v = 0; v < V; ++v) {
       if (!fluid(v)) continue;
+      long c[3];
+      coords(v, c);
+      if (c[axis] < lo || c[axis] >= hi) continue;
       R a = 0.0, b = 0.0;
       for (int i = 0; i < Q; ++i) a += fr[(size_t)i * V + v];
       for (int i = 0; i < Q; ++i) b += fb[(size_t)i * V + v];
@@ -1104,9 +1120,10 @@ int orc_setup_info(const orc_sim* s, uint8_t* cls, double* g3, double* nw3, doub
   return 0;
 }
 
-int orc_objective(orc_sim* s, int objective, double* J) {
+int orc_objective(orc_sim* s, int objective, int axis, int lo, int hi, double* J) {
   if (!s || !J) return fail("null argument");
-  *J = s->s.objective(objective);
+  if (objective < 0 || objective > 2 || axis < 0 || axis >= s->s.D) return fail("bad objective");
+  *J = s->s.objective(objective, axis, lo, hi);
   return 0;
 }
 
@@ -1130,7 +1147,9 @@ int orc_tangent(const orc_params* p, const uint8_t* solid, const double* theta_f
   m.map_contact_angle();
   m.set_phase(phi0);
   for (int k = 0; k < spec->n_steps; ++k) m.step();
-  Dual j = m.objective(spec->objective);
+  if (spec->objective < 0 || spec->objective > 2 || spec->axis < 0 || spec->axis >= m.D)
+    return fail("bad objective");
+  Dual j = m.objective(spec->objective, spec->axis, spec->lo, spec->hi);
   *J = j.v;
   *dJ = j.d;
   return 0;

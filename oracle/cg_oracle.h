@@ -81,10 +81,15 @@ int orc_setup_info(const orc_sim* s, uint8_t* cls, double* g3, double* nw3,
  * seed 0: theta (global, degrees; requires no theta field), seed 1..3: the
  * x/y/z component of the body-force acceleration g, seed 4: the per-voxel
  * contact-angle field along theta_dir (V entries, degrees).
+ * The objectives are taken over the fluid nodes of the slab
+ * lo <= coordinate[axis] < hi of the final state:
  * objective 0: non-wetting mass saturation sum rho^r / sum rho;
- * objective 1: red volume sum (1 + phi)/2 over fluid nodes. */
+ * objective 1: red volume sum (1 + phi)/2;
+ * objective 2: total momentum flux sum rho u_axis over the plane
+ *              coordinate[axis] == lo (u of Eq. 22; hi unused). */
 typedef struct {
   int objective;
+  int axis, lo, hi;
   int n_steps;
   int seed;
   const double* theta_dir;
@@ -92,7 +97,7 @@ typedef struct {
 int orc_tangent(const orc_params* p, const uint8_t* solid, const double* theta_field_deg, const double* phi0,
                 const orc_tangent_spec* spec, double* J, double* dJ);
 /* The objective of the current state of a plain run (same definitions). */
-int orc_objective(orc_sim* s, int objective, double* J);
+int orc_objective(orc_sim* s, int objective, int axis, int lo, int hi, double* J);
 
 /* ---- single-node building blocks, exposed for the pin tests ---- */
 int orc_lattice(int dim, int* e /*[Q][3]*/, double* w, int* opp);
