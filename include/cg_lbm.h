@@ -229,6 +229,71 @@ cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, dou
 cg_status cg_lbm_reset_timing(cg_lbm* h);
 
 /* ---------------------------------------------------------------------- */
+/* Parameters that can change between calls. */
+
+/* New contact angles: the global angle (theta_field_deg NULL) or a per-voxel
+ * field on the solid voxels (dense, V entries, host memory; a fluid boundary
+ * point takes the w_i-weighted mean over its solid link neighbours, as at
+ * creation).  Every angle must lie in (0, 180) degrees.  The Scheme-I secant
+ * start sign follows the new angle.  Synchronises the stream.  A batch that
+ * holds this run sees the new angles (it references the run's arrays). */
+cg_status cg_lbm_set_wetting(cg_lbm* h, double theta_deg, const double* theta_field_deg);
+
+/* New body-force acceleration g (Eq. 36; force density rho_o g).  A batch
+ * created earlier keeps the value it was created with. */
+cg_status cg_lbm_set_body_force(cg_lbm* h, const double g[3]);
+
+/* ---------------------------------------------------------------------- */
+/* Discrete adjoint (reverse mode) of n_steps time steps from the current
+ * state.  J is an objective of the state after n_steps:
+ *   CG_OBJ_SATURATION  sum rho^r / sum rho over the fluid nodes of the slab
+ *                      lo <= coordinate[axis] < hi (the non-wetting mass
+ *                      saturation of Sec. IV.B restricted to a region);
+ *   CG_OBJ_RED_VOLUME  sum (1 + phi)/2 over the same slab (divided by the
+ *                      slab's cross-section it is the volume-based interface
+ *                      position of a displacement along axis);
+ *   CG_OBJ_FLUX        sum rho u_axis (Eq. 22) over the fluid nodes of the
+ *                      plane coordinate[axis] == lo.
+ * The call returns J and its exact discrete derivative (every branch of the
+ * step is held fixed: thresholds, the Scheme-I secant iterations and the
+ * Scheme-II candidate choice) with respect to the global contact angle (per
+ * degree; with a per-voxel field it is the derivative along a uniform shift
+ * of the field), the per-voxel field, and the body-force acceleration g.
+ * The forward sweep stores the state every checkpoint_every = K steps; the
+ * reverse sweep recomputes the K states of one segment at a time into a ring
+ * of K state buffers, so the device memory held during the call is about
+ * (n_steps/K + K + 2) state copies (cg_info.state_bytes each) plus the adjoint
+ * fields.  delta > 0 replaces |C| by max(|C|, delta) in the Jacobian of
+ * n = C/|C| (Eq. 27) only; the forward arithmetic is unchanged; 0 keeps the
+ * exact derivative.  Supported: closed and periodic boundaries with the body
+ * force (CG_BC_NONE); CG_EUNSUPPORTED for Zou-He faces.  The handle's state
+ * and step counter are left as they were.  Synchronises the stream. */
+enum { CG_OBJ_SATURATION = 0, CG_OBJ_RED_VOLUME = 1, CG_OBJ_FLUX = 2 };
+
+typedef struct {
+  int objective;
+  int axis;                  /* 0, 1 or 2 (< dim) */
+  int lo, hi;                /* slab bounds (objectives 0, 1) or the plane (lo, objective 2) */
+  int64_t n_steps;           /* >= 1 */
+  int64_t checkpoint_every;  /* K >= 1 (values above n_steps act as n_steps) */
+  double delta;              /* >= 0 */
+} cg_adjoint_spec;
+
+typedef struct {
+  double J;                  /* out */
+  double dJ_dtheta;          /* out: per degree */
+  double dJ_dg[3];           /* out: per unit of acceleration */
+  double* dJ_dtheta_field;   /* in: NULL or a device buffer of V doubles on the handle's device;
+                                out: dJ/dtheta(x) (per degree) at the solid voxels next to the fluid,
+                                0 elsewhere */
+  double ms_forward;         /* out: GPU time of the forward sweep */
+  double ms_reverse;         /* out: GPU time of the reverse sweep, recomputation included */
+  int64_t work_bytes;        /* out: device memory the call allocated */
+} cg_gradients;
+
+cg_status cg_lbm_adjoint(cg_lbm* h, const cg_adjoint_spec* spec, cg_gradients* out);
+
+/* ---------------------------------------------------------------------- */
 /* Batched runs.  Many runs of one precision, one lattice and one stream
  * advance together: each stage of the step is one persistent launch over a
  * table of (run, tile) pairs for all runs, and the step loop is replayed from

@@ -1,0 +1,888 @@
+// Device code of the discrete adjoint of one colour-gradient time step.
+//
+// The state at time t is the pair of pre-collision populations f^r_i, f^b_i at
+// the fluid nodes; one step is the map t -> t+1 of Sec. II (phase field,
+// extrapolations into the solid boundary points, wetting, curvature and force,
+// velocity, collision, recolouring, pull streaming with halfway bounce-back).
+// Given lambda_{t+1} = dJ/df_{t+1}, one reverse step forms
+//   lambda_t = (d f_{t+1} / d f_t)^T lambda_{t+1}
+// and accumulates the parameter adjoints (dF/dg)^T lambda, (dn/dtheta)^T lambda.
+//
+// The adjoint is kept in a compact form with the same structure as the
+// forward map: lambda^r_i = L_i + R^r, lambda^b_i = L_i + R^b, where L_i is the
+// adjoint of the total population (collision and streaming act on the total)
+// and R^r, R^b collect everything that enters through the colour densities
+// (phase field, recolouring fractions, rates).
+//
+// Every transposed stencil is written as a gather at the receiving node (no
+// atomics; the result does not depend on thread order).  Reverse kernels of a
+// step, after the forward stages of that step were recomputed from its state:
+//   ka_node    reverse streaming (gather of lambda_{t+1} along the pull links,
+//              bounce-back included), then the reverse of recolouring, of the
+//              MRT/BGK collision with Guo forcing, of the velocity, of the
+//              rates; writes L, the node-local density adjoints, lambda kappa,
+//              lambda C from the force, lambda n from the recolouring
+//   ka_curv    transpose of the curvature stencil (Eq. 12) into lambda n, at
+//              fluid nodes and solid boundary points
+//   ka_normal  transpose of the normal extrapolation (Eq. 35) into the fluid,
+//              then the reverse of wetting (Scheme-I / Scheme-II, Jacobian from
+//              a 4-lane forward-mode evaluation of the same code) and of
+//              n = C/|C| (Eq. 27) into lambda C
+//   ka_sb_phi  transpose of the colour-gradient stencil (Eq. 6) at the solid
+//              boundary points
+//   ka_phi     the same at fluid nodes, the transpose of the phase
+//              extrapolation (Eq. 34), and phi = (rho^r - rho^b)/rho: writes R
+#pragma once
+
+#include "kernels.hpp"
+
+namespace cg {
+
+// ------------------------------------------------------- forward-mode lanes
+// A value with four directional derivatives.  Branches compare values only,
+// so the lanes are the derivative of the branch the value takes.
+struct Tan4 {
+  double v;
+  double d[4];
+  __device__ __forceinline__ Tan4() : v(0.0), d{0.0, 0.0, 0.0, 0.0} {}
+  __device__ __forceinline__ Tan4(double a) : v(a), d{0.0, 0.0, 0.0, 0.0} {}
+};
+__device__ __forceinline__ Tan4 operator+(const Tan4& a, const Tan4& b) {
+  Tan4 r(a.v + b.v);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+__device__ __forceinline__ Tan4 operator-(const Tan4& a, const Tan4& b) {
+  Tan4 r(a.v - b.v);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+__device__ __forceinline__ Tan4 operator-(const Tan4& a) {
+  Tan4 r(-a.v);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+__device__ __forceinline__ Tan4 operator*(const Tan4& a, const Tan4& b) {
+  Tan4 r(a.v * b.v);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+__device__ __forceinline__ Tan4 operator/(const Tan4& a, const Tan4& b) {
+  const double q = a.v / b.v;
+  Tan4 r(q);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = (a.d[k] - q * b.d[k]) / b.v;
+  return r;
+}
+__device__ __forceinline__ bool operator<=(const Tan4& a, const Tan4& b) { return a.v <= b.v; }
+__device__ __forceinline__ bool operator<(const Tan4& a, const Tan4& b) { return a.v < b.v; }
+__device__ __forceinline__ Tan4 sqrt(const Tan4& a) {
+  const double s = ::sqrt(a.v);
+  Tan4 r(s);
+  const double h = s > 0.0 ? 0.5 / s : 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * h;
+  return r;
+}
+__device__ __forceinline__ Tan4 fabs(const Tan4& a) { return a.v < 0.0 ? -a : a; }
+
+// --------------------------------------------------------------- buffers
+template <class Real>
+struct Vec2T;
+template <>
+struct Vec2T<float> {
+  using type = float2;
+};
+template <>
+struct Vec2T<double> {
+  using type = double2;
+};
+template <class Real>
+using Vec2 = typename Vec2T<Real>::type;
+
+struct AdjParams {
+  double delta;  // floor of |C| in the Jacobian of C/|C| (0: exact)
+  int objective; // 0 saturation, 1 red volume, 2 plane flux
+  int axis, lo, hi;
+};
+
+template <class Real>
+struct AdjBufs {
+  const Real* lf_in;   // [Q][Np] L at t+1
+  Real* lf_out;        // [Q][Np] L at t
+  Vec2<Real>* lr;      // [Np] (R^r, R^b): read at t+1 by ka_node, rewritten at t by ka_phi
+  Vec4<Real>* na;      // [Np] density adjoints of the node part, dphi/drho^r, dphi/drho^b
+  Vec4<Real>* lcf;     // [Np] lambda C (after wetting) from the force
+  Real* lk;            // [V] lambda kappa at fluid voxels, 0 elsewhere
+  Vec4<Real>* ln;      // [V] lambda n at fluid voxels and solid boundary points
+  Vec4<Real>* lc;      // [V] lambda C (before wetting) at fluid voxels, 0 elsewhere
+  Real* lphi;          // [V] lambda phi / (sum of link weights) at solid boundary points, 0 elsewhere
+  const Real* iden;    // [V] 1 / (sum of fluid-link weights) at solid boundary points, 0 elsewhere
+  const double* idf;   // [Np] 1 / (sum of solid-link weights) at fluid boundary points, 0 elsewhere
+  double4* gacc;       // [Np] sum over steps of lambda F (xyz) and lambda theta (w, per degree)
+  double* lth;         // [V] sum over steps of lambda theta * idf at fluid boundary voxels
+};
+
+__device__ __forceinline__ int coord_of(const StepParams& P, int v, int axis) {
+  const int nxy = P.nx * P.ny;
+  const int z = v / nxy, r = v - z * nxy, y = r / P.nx, x = r - y * P.nx;
+  return axis == 0 ? x : (axis == 1 ? y : z);
+}
+
+// Populations of node n of the state `in` as canonical red and total values
+// (double for the FP64 state; the compact FP32 state keeps g = f^t - w rho0).
+template <class Real, int D, class In>
+__device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G, const In& in, int n, Real* fr,
+                                         Real* fx, Real& rr, Real& rb, Real& rho) {
+  constexpr int Q = Lat<D>::Q;
+  constexpr bool kDev = sizeof(Real) == 4;
+  load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+  Real a = fr[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) a = a + fr[i];
+  rr = a;
+  if constexpr (kDev) {
+    Real t = (Real)Lat<D>::w(0) * (Real)P.rho0 + fx[0];
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      t = t + ((Real)Lat<D>::w(i) * (Real)P.rho0 + fx[i]);
+    });
+    rho = t;
+    rb = t - a;
+  } else {
+    Real b = fx[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) b = b + fx[i];
+    rb = b;
+    rho = a + b;
+  }
+}
+
+// ------------------------------------------------------------------ ka_node
+// kSeed: no lambda_{t+1}; instead the plane-flux objective J = sum (j + F/2)_axis
+// is seeded at the plane nodes (the terminal condition of objective 2).
+template <class Real, int D, bool kSeed, class In>
+__device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
+                                           const In& in, const AdjBufs<Real>& A, const AdjParams& AP, int n) {
+  constexpr int Q = Lat<D>::Q;
+  constexpr bool kDev = sizeof(Real) == 4;
+  using CT = Real;
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  // reverse streaming: c_j(x) became f_j(x + e_j) when that voxel is fluid,
+  // else f_opp(j)(x) (halfway bounce-back)
+  CT lcr[Q], lcb[Q];
+  if constexpr (kSeed) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      lcr[i] = CT(0);
+      lcb[i] = CT(0);
+    }
+  } else {
+    const Vec2<Real> own = A.lr[n];
+    unroll<Q>([&](auto J) {
+      constexpr int j = J;
+      if constexpr (j == 0) {
+        const CT l = A.lf_in[n];
+        lcr[0] = l + own.x;
+        lcb[0] = l + own.y;
+      } else {
+        constexpr int o = opp<D>(j);
+        const int s = G.nbr[(o - 1) * P.Np + n];  // node at x - e_o = x + e_j
+        CT l;
+        Vec2<Real> r;
+        if (s >= 0) {
+          l = A.lf_in[j * P.Np + s];
+          r = A.lr[s];
+        } else {
+          l = A.lf_in[o * P.Np + n];
+          r = own;
+        }
+        lcr[j] = l + r.x;
+        lcb[j] = l + r.y;
+      }
+    });
+  }
+  // forward quantities of the step at t
+  Real fr[Q], fx[Q];
+  Real rr, rb, rho;
+  adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+  const CT rho0 = (CT)P.rho0;
+  CT drho;  // density handed to the equilibrium (deviation for the compact state)
+  if constexpr (kDev) {
+    CT s = fx[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) s = s + fx[i];
+    drho = s;
+  } else {
+    drho = rho;
+  }
+  const CT rho_u = kDev ? rho0 + drho : rho;
+  const Vec4<Real> f4 = R.f[n];
+  const Vec4<Real> n4 = R.n[v];
+  const Vec4<Real> c4 = R.c[n];
+  const CT F[3] = {(CT)f4.x, (CT)f4.y, (CT)f4.z};
+  const CT kap = (CT)f4.w;
+  const CT nv[3] = {(CT)n4.x, (CT)n4.y, (CT)n4.z};
+  const CT Cv[3] = {(CT)c4.x, (CT)c4.y, (CT)c4.z};
+  const CT phi = (CT)R.phi[v];
+  CT u[3] = {CT(0), CT(0), CT(0)};
+  unroll<D>([&](auto A_) {
+    constexpr int a = A_;
+    CT j = CT(0);
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int e = Lat<D>::e(i, a);
+      const CT ft_i = kDev ? (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
+      if constexpr (e == 1) j = j + ft_i;
+      if constexpr (e == -1) j = j - ft_i;
+    });
+    u[a] = (j + CT(0.5) * F[a]) / rho_u;
+  });
+  CT usq = u[0] * u[0] + u[1] * u[1];
+  if constexpr (D == 3) usq = usq + u[2] * u[2];
+  CT s_nu, s_q;
+  rates(P, phi, s_nu, s_q);
+  // y = f - f^eq + Fbar/2 and Fbar
+  CT y[Q], gu[Q];
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    const CT fe = eq_i<D, i>(drho, rho0, u, usq);
+    gu[i] = guo_i<D, i>(u, F);
+    const CT base = kDev ? (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
+    y[i] = base - fe + CT(0.5) * gu[i];
+  });
+  const CT ra = (CT)rr / (CT)rho;
+  const CT rbb = (CT)rr * (CT)rb / (CT)rho;
+  // reverse of recolouring, Eqs. (20)-(21): c^r = a f'' + beta w b e.n, c^b = f'' - c^r
+  CT dl[Q], mu[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    dl[i] = lcr[i] - lcb[i];
+    mu[i] = lcb[i] + ra * dl[i];
+  }
+  // collision f'' = f + Fbar - M^-1 S M y (BGK: M = I, S = s_nu); post-collision
+  // totals, lambda y and the rate adjoints
+  CT ly[Q], la = CT(0), lsnu = CT(0), lsq = CT(0);
+  auto bgk = [&]() {
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      const CT base = kDev ? (CT)Lat<D>::w(i) * rho0 + (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
+      const CT out = base + gu[i] - s_nu * y[i];
+      la = la + out * dl[i];
+      lsnu = lsnu - mu[i] * y[i];
+      ly[i] = -s_nu * mu[i];
+    });
+  };
+  if constexpr (D == 3) {
+    if (P.collision == 1) {
+      CT my[19], nu[19];
+      unroll<19>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (rate_class(k) != 0) {
+          CT a = CT(0), b = CT(0);
+          unroll<19>([&](auto I) {
+            constexpr int i = I;
+            constexpr int m = Mkj(k, i);
+            if constexpr (m != 0) {
+              a = a + (CT)m * y[i];
+              b = b + (CT)m * mu[i];
+            }
+          });
+          constexpr CT inorm = (CT)(1.0 / (double)Mnorm2(k));
+          const CT S = rate_class(k) == 1 ? s_nu : s_q;
+          // lambda S_k = -(M^-T mu)_k (M y)_k
+          if constexpr (rate_class(k) == 1)
+            lsnu = lsnu - b * inorm * a;
+          else
+            lsq = lsq - b * inorm * a;
+          my[k] = S * a * inorm;
+          nu[k] = S * b * inorm;
+        }
+      });
+      unroll<19>([&](auto I) {
+        constexpr int i = I;
+        CT s = CT(0), t = CT(0);
+        unroll<19>([&](auto K) {
+          constexpr int k = K;
+          constexpr int m = Mkj(k, i);
+          if constexpr (rate_class(k) != 0 && m != 0) {
+            s = s + (CT)m * my[k];
+            t = t + (CT)m * nu[k];
+          }
+        });
+        const CT base = kDev ? (CT)Lat<D>::w(i) * rho0 + (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
+        const CT out = base + gu[i] - s;
+        la = la + out * dl[i];
+        ly[i] = -t;
+      });
+    } else {
+      bgk();
+    }
+  } else {
+    bgk();
+  }
+  // lambda of f (total), f^eq and Fbar
+  CT lft[Q];
+  CT lrho = CT(0), lu[3] = {CT(0), CT(0), CT(0)}, lF[3] = {CT(0), CT(0), CT(0)};
+  CT lb = CT(0), lnr[3] = {CT(0), CT(0), CT(0)};
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    constexpr double w = Lat<D>::w(i);
+    lft[i] = mu[i] + ly[i];
+    const CT lfe = -ly[i];
+    const CT lgu = mu[i] + CT(0.5) * ly[i];
+    CT eu = CT(0), eF = CT(0);
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr int e = Lat<D>::e(i, a);
+      if constexpr (e == 1) {
+        eu = eu + u[a];
+        eF = eF + F[a];
+      }
+      if constexpr (e == -1) {
+        eu = eu - u[a];
+        eF = eF - F[a];
+      }
+    });
+    // f^eq_i = w [rho + rho0 (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]
+    lrho = lrho + (CT)w * lfe;
+    const CT qe = (CT)w * lfe * rho0;
+    // Fbar_i = w [3 (e - u).F + 9 (e.u)(e.F)]
+    const CT qg = (CT)w * lgu;
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr CT e = (CT)Lat<D>::e(i, a);
+      lu[a] = lu[a] + qe * (CT(3) * e + CT(9) * eu * e - CT(3) * u[a]) + qg * (CT(-3) * F[a] + CT(9) * eF * e);
+      lF[a] = lF[a] + qg * (CT(3) * (e - u[a]) + CT(9) * eu * e);
+    });
+    if constexpr (i > 0) {
+      CT en = CT(0);
+      unroll<D>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<D>::e(i, a);
+        if constexpr (e == 1) en = en + nv[a];
+        if constexpr (e == -1) en = en - nv[a];
+      });
+      const CT q = (CT)(P.beta * w) * dl[i];
+      lb = lb + q * en;
+      unroll<D>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<D>::e(i, a);
+        if constexpr (e == 1) lnr[a] = lnr[a] + q;
+        if constexpr (e == -1) lnr[a] = lnr[a] - q;
+      });
+    }
+  });
+#pragma unroll
+  for (int a = 0; a < D; ++a) lnr[a] = lnr[a] * rbb;
+  // rates, Eqs. (13)-(16): S_nu(phi), S_q(S_nu)
+  {
+    const CT inv_nu = (CT(1) + phi) / (CT(2) * (CT)P.nu_r) + (CT(1) - phi) / (CT(2) * (CT)P.nu_b);
+    const CT nuv = CT(1) / inv_nu;
+    const CT dinv = CT(1) / (CT(2) * (CT)P.nu_r) - CT(1) / (CT(2) * (CT)P.nu_b);
+    const CT dsdphi = CT(3) * s_nu * s_nu * nuv * nuv * dinv;
+    const CT dq = CT(-48) / ((CT(8) - s_nu) * (CT(8) - s_nu));
+    lsnu = lsnu + lsq * dq;
+    lsnu = lsnu * dsdphi;  // now lambda phi (node part)
+  }
+  // velocity, Eq. (22): u = (j + F/2) / rho
+  CT lj[3] = {CT(0), CT(0), CT(0)};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lj[a] = lu[a] / rho_u;
+    lF[a] = lF[a] + CT(0.5) * lj[a];
+    lrho = lrho - lj[a] * u[a];
+  }
+  if constexpr (kSeed) {
+    if (coord_of(P, v, AP.axis) == AP.lo) {
+      lj[AP.axis] = lj[AP.axis] + CT(1);
+      lF[AP.axis] = lF[AP.axis] + CT(0.5);
+    }
+  }
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr int e = Lat<D>::e(i, a);
+      if constexpr (e == 1) lft[i] = lft[i] + lj[a];
+      if constexpr (e == -1) lft[i] = lft[i] - lj[a];
+    });
+  });
+  // recolouring fractions a = rho^r/rho, b = rho^r rho^b / rho
+  const CT irho = CT(1) / (CT)rho;
+  CT lrr = la * irho + lb * (CT)rb * irho;
+  CT lrb = lb * (CT)rr * irho;
+  lrho = lrho - (la * ra + lb * rbb) * irho;
+  lrr = lrr + lrho;
+  lrb = lrb + lrho;
+  // phi = (rho^r - rho^b) / rho
+  const CT dr = CT(2) * (CT)rb * irho * irho;
+  const CT db = CT(-2) * (CT)rr * irho * irho;
+  // force F = sigma/2 kappa C + rho0 g
+  CT lkap = CT(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) lkap = lkap + lF[a] * Cv[a];
+  lkap = lkap * (CT)P.half_sigma;
+  const CT hk = (CT)P.half_sigma * kap;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) A.lf_out[i * P.Np + n] = lft[i];
+  Vec4<Real> na;
+  na.x = lrr + lsnu * dr;
+  na.y = lrb + lsnu * db;
+  na.z = dr;
+  na.w = db;
+  A.na[n] = na;
+  Vec4<Real> q;
+  q.x = hk * lF[0];
+  q.y = hk * lF[1];
+  q.z = D == 3 ? hk * lF[2] : Real(0);
+  q.w = Real(0);
+  A.lcf[n] = q;
+  A.lk[v] = lkap;
+  Vec4<Real> l4;
+  l4.x = lnr[0];
+  l4.y = lnr[1];
+  l4.z = D == 3 ? lnr[2] : Real(0);
+  l4.w = Real(0);
+  A.ln[v] = l4;
+  double4 g = A.gacc[n];
+  g.x += (double)lF[0];
+  g.y += (double)lF[1];
+  if constexpr (D == 3) g.z += (double)lF[2];
+  A.gacc[n] = g;
+}
+
+template <class Real, int D, bool kSeed, class In>
+__global__ void __launch_bounds__(256) ka_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A, AdjParams AP) {
+  const int n = node_id();
+  if (n < P.N) d_adj_node<Real, D, kSeed, In>(P, G, R, in, A, AP, n);
+}
+
+// ------------------------------------------------------------------ ka_curv
+// kappa(x) = sum_ab (n_a n_b - delta_ab) d_b n_a with d_b n_a = 3 sum_i w_i e_ib n_a(x + e_i):
+//   at y = x + e_i: lambda n_a(y) += 3 w_i lambda kappa(x) (n_a(x) (e_i.n(x)) - e_ia)
+//   at x itself:    lambda n_a(x) += lambda kappa(x) sum_b (d_b n_a + d_a n_b) n_b
+// Written as a gather at y over x = y + e_j (e_j = -e_i).
+template <class Real, int D, bool kSb>
+__device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
+                                           const AdjBufs<Real>& A, int idx) {
+  constexpr int Q = Lat<D>::Q;
+  using CT = Real;
+  int v;
+  bool face;
+  if constexpr (kSb) {
+    if (idx >= P.nsb) return;
+    v = G.sb_vox[idx];
+    face = G.sb_mask[idx] & 1u;
+  } else {
+    if (idx >= P.N) return;
+    const unsigned vf = G.vf[idx];
+    v = vox_of(vf);
+    face = flags_of(vf) & FL_FACE;
+  }
+  const Pos ps = make_pos(P, v, face);
+  CT acc[3] = {CT(0), CT(0), CT(0)};
+  CT d[3][3] = {{CT(0), CT(0), CT(0)}, {CT(0), CT(0), CT(0)}, {CT(0), CT(0), CT(0)}};
+  unroll<Q - 1>([&](auto J) {
+    constexpr int j = J + 1;
+    constexpr double w = Lat<D>::w(j);
+    const int x = nb_vox<D, j>(P, ps);
+    const Vec4<Real> q = R.n[x];
+    const CT nq[3] = {(CT)q.x, (CT)q.y, (CT)q.z};
+    const CT lk = (CT)A.lk[x];
+    CT en = CT(0);
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr int e = Lat<D>::e(j, a);
+      if constexpr (e == 1) en = en + nq[a];
+      if constexpr (e == -1) en = en - nq[a];
+    });
+    const CT c = (CT)(3.0 * w) * lk;
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr CT e = (CT)Lat<D>::e(j, a);
+      acc[a] = acc[a] + c * (e - nq[a] * en);
+    });
+    if constexpr (!kSb) {
+      unroll<D>([&](auto B_) {
+        constexpr int b = B_;
+        constexpr int e = Lat<D>::e(j, b);
+        if constexpr (e != 0) {
+          unroll<D>([&](auto A_) {
+            constexpr int a = A_;
+            d[b][a] = d[b][a] + (CT)(3.0 * w * e) * nq[a];
+          });
+        }
+      });
+    }
+  });
+  Vec4<Real> o;
+  if constexpr (!kSb) {
+    const Vec4<Real> s4 = R.n[v];
+    const CT ns[3] = {(CT)s4.x, (CT)s4.y, (CT)s4.z};
+    const CT lk = (CT)A.lk[v];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      CT t = CT(0);
+#pragma unroll
+      for (int b = 0; b < D; ++b) t = t + (d[b][a] + d[a][b]) * ns[b];
+      acc[a] = acc[a] + lk * t;
+    }
+    o = A.ln[v];
+    o.x = o.x + acc[0];
+    o.y = o.y + acc[1];
+    if constexpr (D == 3) o.z = o.z + acc[2];
+  } else {
+    o.x = acc[0];
+    o.y = acc[1];
+    o.z = D == 3 ? acc[2] : CT(0);
+    o.w = Real(0);
+  }
+  A.ln[v] = o;
+}
+
+template <class Real, int D, bool kSb>
+__global__ void ka_curv(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A) {
+  d_adj_curv<Real, D, kSb>(P, G, R, A, node_id());
+}
+
+// ---------------------------------------------------------------- ka_normal
+template <class Real, int D>
+__device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
+                                             const AdjBufs<Real>& A, const AdjParams& AP, int n) {
+  constexpr int Q = Lat<D>::Q;
+  using CT = double;
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const unsigned fl = flags_of(vf);
+  const Pos ps = make_pos(P, v, fl & FL_FACE);
+  const double idf = A.idf[n];
+  // lambda n: own part plus the transpose of Eq. (35) from the solid boundary
+  // points next to a fluid boundary point
+  const Vec4<Real> l4 = A.ln[v];
+  CT ln[3] = {(CT)l4.x, (CT)l4.y, (CT)l4.z};
+  if (idf != 0.0) {
+    unroll<Q - 1>([&](auto J) {
+      constexpr int j = J + 1;
+      const int x = nb_vox<D, j>(P, ps);
+      const Real id = A.iden[x];
+      if (id != Real(0)) {
+        const Vec4<Real> q = A.ln[x];
+        const CT c = (CT)Lat<D>::w(j) * (CT)id;
+        ln[0] = ln[0] + c * (CT)q.x;
+        ln[1] = ln[1] + c * (CT)q.y;
+        if constexpr (D == 3) ln[2] = ln[2] + c * (CT)q.z;
+      }
+    });
+  }
+  const Vec4<Real> f4 = A.lcf[n];
+  const CT lco[3] = {(CT)f4.x, (CT)f4.y, (CT)f4.z};
+  // colour gradient before wetting, Eq. (6)
+  CT C[3] = {CT(0), CT(0), CT(0)};
+  unroll<Q - 1>([&](auto J) {
+    constexpr int j = J + 1;
+    const CT ph = (CT)R.phi[nb_vox<D, j>(P, ps)];
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr int e = Lat<D>::e(j, a);
+      if constexpr (e != 0) C[a] = C[a] + (CT)(3.0 * Lat<D>::w(j) * e) * ph;
+    });
+  });
+  const CT cm = ::sqrt(dotv<CT, D>(C, C));
+  CT lci[3] = {lco[0], lco[1], lco[2]};
+  double lth = 0.0;
+  if (cm > (CT)P.eps_c) {
+    CT ch[3] = {C[0] / cm, C[1] / cm, D == 3 ? C[2] / cm : CT(0)};
+    CT lch[3], lcm = CT(0);
+    if ((fl & FL_WET) && P.scheme != 0) {
+      Tan4 nn[3], w3[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        nn[a] = Tan4(ch[a]);
+        if (a < D) nn[a].d[a] = 1.0;
+        w3[a] = Tan4(a < D ? (double)G.nw[a * P.Np + n] : 0.0);
+      }
+      constexpr double deg = 3.14159265358979323846 / 180.0;
+      const double ctv = (double)G.cos_t[n], stv = (double)G.sin_t[n];
+      Tan4 ct(ctv), st(stv);
+      ct.d[3] = -stv * deg;
+      st.d[3] = ctv * deg;
+      if (P.scheme == 1)
+        scheme1<Tan4, D>(nn, w3, ct, Tan4((fl & FL_S1POS) ? 1.0 : -1.0), Tan4(P.eps_f), Tan4(P.eps_v));
+      else
+        scheme2<Tan4, D>(nn, w3, ct, st, Tan4(P.eps_v));
+      // C_out = |C| n_wet
+      CT lnt[3];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        lnt[b] = ln[b] + cm * lco[b];
+        lcm = lcm + nn[b].v * lco[b];
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        CT s = CT(0);
+#pragma unroll
+        for (int b = 0; b < D; ++b) s = s + nn[b].d[a] * lnt[b];
+        lch[a] = s;
+      }
+#pragma unroll
+      for (int b = 0; b < D; ++b) lth += nn[b].d[3] * lnt[b];
+#pragma unroll
+      for (int a = 0; a < D; ++a) lci[a] = CT(0);
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) lch[a] = ln[a];
+    }
+    // n = C / |C|: (I - n n^T) / |C|
+    const CT cd = cm > (CT)AP.delta ? cm : (CT)AP.delta;
+    CT dp = CT(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) dp = dp + ch[a] * lch[a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) lci[a] = lci[a] + lcm * ch[a] + (lch[a] - ch[a] * dp) / cd;
+  }
+  Vec4<Real> o;
+  o.x = (Real)lci[0];
+  o.y = (Real)lci[1];
+  o.z = D == 3 ? (Real)lci[2] : Real(0);
+  o.w = Real(0);
+  A.lc[v] = o;
+  if (lth != 0.0) {
+    double4 g = A.gacc[n];
+    g.w += lth;
+    A.gacc[n] = g;
+    A.lth[v] += lth * idf;
+  }
+}
+
+template <class Real, int D>
+__global__ void __launch_bounds__(256) ka_normal(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A, AdjParams AP) {
+  const int n = node_id();
+  if (n < P.N) d_adj_normal<Real, D>(P, G, R, A, AP, n);
+}
+
+// ------------------------------------------------------- ka_sb_phi, ka_phi
+// C(x) = 3 sum_i w_i e_i phi(x + e_i)  =>  lambda phi(y) = -3 sum_j w_j e_j . lambda C(y + e_j)
+template <class Real, int D>
+__device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Real>& A, const Pos& ps) {
+  constexpr int Q = Lat<D>::Q;
+  Real acc = Real(0);
+  unroll<Q - 1>([&](auto J) {
+    constexpr int j = J + 1;
+    const Vec4<Real> q = A.lc[nb_vox<D, j>(P, ps)];
+    const Real qq[3] = {q.x, q.y, q.z};
+    Real t = Real(0);
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr int e = Lat<D>::e(j, a);
+      if constexpr (e == 1) t = t + qq[a];
+      if constexpr (e == -1) t = t - qq[a];
+    });
+    acc = acc + (Real)(-3.0 * Lat<D>::w(j)) * t;
+  });
+  return acc;
+}
+
+template <class Real, int D>
+__global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
+  const int s = node_id();
+  if (s >= P.nsb) return;
+  const int v = G.sb_vox[s];
+  const Pos ps = make_pos(P, v, G.sb_mask[s] & 1u);
+  A.lphi[v] = adj_grad_t<Real, D>(P, A, ps) * A.iden[v];
+}
+
+template <class Real, int D>
+__global__ void ka_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
+  constexpr int Q = Lat<D>::Q;
+  const int n = node_id();
+  if (n >= P.N) return;
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
+  Real lp = adj_grad_t<Real, D>(P, A, ps);
+  if (A.idf[n] != 0.0) {
+    // transpose of Eq. (34): phi(s) = sum_i w_i phi(s + e_i) / sum_i w_i
+    unroll<Q - 1>([&](auto J) {
+      constexpr int j = J + 1;
+      lp = lp + (Real)Lat<D>::w(j) * A.lphi[nb_vox<D, j>(P, ps)];
+    });
+  }
+  const Vec4<Real> na = A.na[n];
+  Vec2<Real> r;
+  r.x = na.x + lp * na.z;
+  r.y = na.y + lp * na.w;
+  A.lr[n] = r;
+}
+
+// -------------------------------------------------------- objective, seeds
+// Per-block partial sums over the objective's slab (or plane): rho^r, rho^b,
+// (1 + phi)/2, and the plane flux (j + F/2)_axis.
+constexpr int kObjN = 4;
+
+template <class Real, int D, int BS, class In>
+__global__ void __launch_bounds__(BS) ka_obj(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjParams AP,
+                                             double* part) {
+  constexpr int Q = Lat<D>::Q;
+  constexpr bool kDev = sizeof(Real) == 4;
+  const int n = node_id();
+  double o[kObjN] = {0.0, 0.0, 0.0, 0.0};
+  if (n < P.N) {
+    const int v = vox_of(G.vf[n]);
+    const int c = coord_of(P, v, AP.axis);
+    Real fr[Q], fx[Q], rr, rb, rho;
+    adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+    if (c >= AP.lo && c < AP.hi) {
+      o[0] = (double)rr;
+      o[1] = (double)rb;
+      o[2] = (1.0 + ((double)rr - (double)rb) / (double)rho) / 2.0;
+    }
+    if (c == AP.lo && AP.objective == 2) {
+      double j = 0.0;
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        const double ft = kDev ? (double)fx[i] : (double)fr[i] + (double)fx[i];
+        constexpr int e0 = Lat<D>::e(i, 0), e1 = Lat<D>::e(i, 1), e2 = Lat<D>::e(i, 2);
+        const int e = AP.axis == 0 ? e0 : (AP.axis == 1 ? e1 : e2);
+        j += (double)e * ft;
+      });
+      const Vec4<Real> f4 = R.f[n];
+      const double Fa = AP.axis == 0 ? (double)f4.x : (AP.axis == 1 ? (double)f4.y : (double)f4.z);
+      o[3] = j + 0.5 * Fa;
+    }
+  }
+  __shared__ double sh[BS / 64];
+#pragma unroll
+  for (int q = 0; q < kObjN; ++q) {
+    const double t = block_sum<BS>(o[q], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * kObjN + q] = t;
+  }
+}
+
+// Fixed-order reduction of [nb][nq] partials: one block per quantity.
+// (Templated on the precision only so that each precision's translation unit
+// owns its own instance.)
+template <class Real>
+__global__ void ka_reduce(const double* part, int nb, int nq, double* out) {
+  const int q = blockIdx.x;
+  __shared__ double sh[256];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) t += part[(size_t)b * nq + q];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = sh[0];
+}
+
+// Terminal adjoint of objectives 0 and 1 (node-local in the densities):
+// saturation J = S_r / (S_r + S_b): dJ/drho^r = S_b / S^2, dJ/drho^b = -S_r / S^2;
+// red volume J = sum (1 + phi)/2: dJ/drho^r = rho^b / rho^2, dJ/drho^b = -rho^r / rho^2.
+template <class Real, int D, class In>
+__global__ void ka_seed_local(StepParams P, Geo<Real> G, In in, AdjParams AP, const double* sums, Real* lf,
+                              Vec2<Real>* lr) {
+  constexpr int Q = Lat<D>::Q;
+  const int n = node_id();
+  if (n >= P.N) return;
+  const int v = vox_of(G.vf[n]);
+  const int c = coord_of(P, v, AP.axis);
+  double gr = 0.0, gb = 0.0;
+  if (c >= AP.lo && c < AP.hi) {
+    if (AP.objective == 0) {
+      const double S = sums[0] + sums[1];
+      gr = sums[1] / (S * S);
+      gb = -sums[0] / (S * S);
+    } else {
+      Real fr[Q], fx[Q], rr, rb, rho;
+      adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+      const double ir = 1.0 / (double)rho;
+      gr = (double)rb * ir * ir;
+      gb = -(double)rr * ir * ir;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lf[i * P.Np + n] = Real(0);
+  Vec2<Real> r;
+  r.x = (Real)gr;
+  r.y = (Real)gb;
+  lr[n] = r;
+}
+
+// ------------------------------------------------------------ setup, output
+// 1 / (sum of the weights of the fluid links) at each solid boundary point.
+template <class Real, int D>
+__global__ void ka_iden(StepParams P, Geo<Real> G, Real* iden) {
+  constexpr int Q = Lat<D>::Q;
+  const int s = node_id();
+  if (s >= P.nsb) return;
+  const unsigned m = G.sb_mask[s];
+  double den = 0.0;
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    if (m & (1u << i)) den += Lat<D>::w(i);
+  });
+  iden[G.sb_vox[s]] = (Real)(1.0 / den);
+}
+
+// 1 / (sum of the weights of the solid links) at each fluid boundary point
+// (links whose pull source is a solid voxel; the lattice is symmetric).
+template <class Real, int D>
+__global__ void ka_idf(StepParams P, Geo<Real> G, double* idf) {
+  constexpr int Q = Lat<D>::Q;
+  const int n = node_id();
+  if (n >= P.N) return;
+  double den = 0.0;
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    if (G.nbr[(i - 1) * P.Np + n] == kBounce) den += Lat<D>::w(i);
+  });
+  idf[n] = den > 0.0 ? 1.0 / den : 0.0;
+}
+
+// Per-block partial sums of the accumulated parameter adjoints.
+template <class Real, int BS>
+__global__ void __launch_bounds__(BS) ka_grad_part(int N, const double4* gacc, double* part) {
+  const int n = node_id();
+  double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (n < N) g = gacc[n];
+  __shared__ double sh[BS / 64];
+  const double q[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double t = block_sum<BS>(q[k], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * 4 + k] = t;
+  }
+}
+
+// dJ/dtheta(s) at each solid boundary point: the transpose of the weighted
+// mean that gives a fluid boundary point its angle (w_i over its solid links).
+template <class Real, int D>
+__global__ void ka_theta_field(StepParams P, Geo<Real> G, const double* lth, double* out) {
+  constexpr int Q = Lat<D>::Q;
+  const int s = node_id();
+  if (s >= P.nsb) return;
+  const int v = G.sb_vox[s];
+  const unsigned m = G.sb_mask[s];
+  const Pos ps = make_pos(P, v, m & 1u);
+  double acc = 0.0;
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    if (m & (1u << i)) acc += Lat<D>::w(i) * lth[nb_vox<D, i>(P, ps)];
+  });
+  out[v] = acc;
+}
+
+template <class Real, class T>
+__global__ void ka_fill(size_t count, T* p, T value) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+}  // namespace cg

@@ -1,0 +1,334 @@
+// Host driver of the discrete adjoint: forward sweep with checkpoints every K
+// steps, then segment by segment (last first) the K states of the segment are
+// recomputed from its checkpoint into a ring of state buffers and the reverse
+// steps run from the last state of the segment down to its checkpoint.
+// Included at the end of engine.hpp (needs the complete Engine).
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+#include "adjoint.hpp"
+
+namespace cg {
+
+template <class Real>
+class AdjointRun {
+  using V4 = Vec4<Real>;
+  using V2 = Vec2<Real>;
+  static constexpr bool kF32 = sizeof(Real) == 4;
+  static constexpr int BS = Engine<Real>::BS;
+
+ public:
+  explicit AdjointRun(Engine<Real>& e) : E(e) {}
+  ~AdjointRun() {
+    (void)hipStreamSynchronize(E.stream_);
+    for (void* p : mem_) E.al_->put(p);
+    for (hipEvent_t ev : ev_) (void)hipEventDestroy(ev);
+  }
+
+  int run(const cg_adjoint_spec& sp, cg_gradients* g) {
+    const StepParams& P = E.P_;
+    if (P.bc != 0) {
+      E.err_ = "the adjoint covers closed and periodic boundaries with the body force (no Zou-He faces)";
+      return CG_EUNSUPPORTED;
+    }
+    if (sp.n_steps < 1 || sp.checkpoint_every < 1) {
+      E.err_ = "n_steps and checkpoint_every must be >= 1";
+      return CG_EINVAL;
+    }
+    if (sp.objective < 0 || sp.objective > 2 || sp.axis < 0 || sp.axis >= E.dim_ || !(sp.delta >= 0.0)) {
+      E.err_ = "bad objective, axis or delta";
+      return CG_EINVAL;
+    }
+    AP_.delta = sp.delta;
+    AP_.objective = sp.objective;
+    AP_.axis = sp.axis;
+    AP_.lo = sp.lo;
+    AP_.hi = sp.hi;
+    return E.dim_ == 3 ? run_d<3>(sp, g) : run_d<2>(sp, g);
+  }
+
+ private:
+  Engine<Real>& E;
+  AdjParams AP_{};
+  std::vector<void*> mem_;
+  std::vector<hipEvent_t> ev_;
+  size_t bytes_ = 0;
+  struct Slot {
+    void* a = nullptr;
+    void* b = nullptr;
+  };
+  // adjoint buffers
+  Real* lf_[2] = {nullptr, nullptr};
+  V2* lr_ = nullptr;
+  V4 *na_ = nullptr, *lcf_ = nullptr, *ln_ = nullptr, *lc_ = nullptr;
+  Real *lk_ = nullptr, *lphi_ = nullptr, *iden_ = nullptr;
+  double *idf_ = nullptr, *lth_ = nullptr, *part_ = nullptr, *sums_ = nullptr;
+  double4* gacc_ = nullptr;
+  int p_ = 0;  // the current adjoint lives in lf_[p_], lr_
+
+  void* get(size_t b) {
+    void* p = E.al_->get(b);
+    if (p) {
+      mem_.push_back(p);
+      bytes_ += b;
+    }
+    return p;
+  }
+  bool new_slot(Slot* s) {
+    const size_t Q = E.Q_, Np = E.P_.Np;
+    if (kF32) {
+      s->a = get(sizeof(float) * Q * Np);
+      s->b = get(sizeof(float4) * Np);
+    } else {
+      s->a = get(sizeof(Real) * Q * Np);
+      s->b = get(sizeof(Real) * Q * Np);
+    }
+    return s->a && s->b;
+  }
+  template <int D>
+  auto in_of(const Slot& s) const {
+    if constexpr (kF32)
+      return InCompact<D>{(const float*)s.a, (const float4*)s.b, E.P_.Np, (float)E.P_.rho0};
+    else
+      return InCanon<Real, D>{(const Real*)s.a, (const Real*)s.b, E.P_.Np};
+  }
+  template <int D>
+  auto out_of(const Slot& s) const {
+    if constexpr (kF32)
+      return OutCompact<D>{(float*)s.a, (float4*)s.b, E.P_.Np};
+    else
+      return OutCanon<Real, D>{(Real*)s.a, (Real*)s.b, E.P_.Np};
+  }
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) == hipSuccess) ev_.push_back(e);
+    return e;
+  }
+  AdjBufs<Real> bufs() const {
+    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_, na_, lcf_, lk_, ln_, lc_, lphi_, iden_, idf_, gacc_, lth_};
+  }
+
+  // one forward step from `in` into slot `out`
+  template <int D, class In>
+  void fstep(const In& in, const Slot& out) {
+    auto o = out_of<D>(out);
+    E.template front_with<D>(in, 5);
+    E.launch(-1, k_main<Real, D, BS, MODE_STEP, In, decltype(o)>, E.P_.N, E.P_, E.G_, E.R_, in, o, MacroOut{},
+             ObsOut{});
+  }
+
+  // the reverse stages after the node stage (shared by the steps and the
+  // flux terminal condition)
+  template <int D>
+  void reverse_tail() {
+    const StepParams& P = E.P_;
+    const AdjBufs<Real> A = bufs();
+    E.launch(-1, ka_curv<Real, D, false>, P.N, P, E.G_, E.R_, A);
+    if (P.nsb) E.launch(-1, ka_curv<Real, D, true>, P.nsb, P, E.G_, E.R_, A);
+    E.launch(-1, ka_normal<Real, D>, P.N, P, E.G_, E.R_, A, AP_);
+    if (P.nsb) E.launch(-1, ka_sb_phi<Real, D>, P.nsb, P, E.G_, A);
+    E.launch(-1, ka_phi<Real, D>, P.N, P, E.G_, A);
+    p_ ^= 1;
+  }
+
+  // lambda_{t} from lambda_{t+1}, the state at t being `in`
+  template <int D, class In>
+  void rstep(const In& in) {
+    const StepParams& P = E.P_;
+    E.template front_with<D>(in, 5);
+    E.launch(-1, ka_node<Real, D, false, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
+    reverse_tail<D>();
+  }
+
+  // objective of the state `in` (into sums_) and the terminal adjoint
+  template <int D, class In>
+  void terminal(const In& in) {
+    const StepParams& P = E.P_;
+    E.template front_with<D>(in, 5);
+    const int nb = (P.N + BS - 1) / BS;
+    E.launch(-1, ka_obj<Real, D, BS, In>, P.N, P, E.G_, E.R_, in, AP_, part_);
+    hipLaunchKernelGGL(ka_reduce<Real>, dim3(kObjN), dim3(256), 0, E.stream_, (const double*)part_, nb, kObjN, sums_);
+    if (AP_.objective == 2) {
+      E.launch(-1, ka_node<Real, D, true, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
+      reverse_tail<D>();
+    } else {
+      E.launch(-1, ka_seed_local<Real, D, In>, P.N, P, E.G_, in, AP_, (const double*)sums_, lf_[p_], lr_);
+    }
+  }
+
+  template <int D>
+  int run_d(const cg_adjoint_spec& sp, cg_gradients* g) {
+    const StepParams& P = E.P_;
+    const size_t Np = P.Np, V = P.V, Q = E.Q_;
+    const int64_t T = sp.n_steps;
+    const int64_t K = std::min<int64_t>(sp.checkpoint_every, T);
+    const int64_t nseg = (T + K - 1) / K;
+    const int64_t Llast = T - (nseg - 1) * K;
+    // state buffers: checkpoints 1..nseg-1, two temporaries, the ring of K
+    std::vector<Slot> ck((size_t)(nseg - 1)), tmp(2), ring((size_t)K);
+    bool ok = true;
+    for (auto& s : ck) ok = ok && new_slot(&s);
+    for (auto& s : tmp) ok = ok && new_slot(&s);
+    for (auto& s : ring) ok = ok && new_slot(&s);
+    for (int k = 0; k < 2; ++k) lf_[k] = (Real*)get(sizeof(Real) * Q * Np);
+    lr_ = (V2*)get(sizeof(V2) * Np);
+    na_ = (V4*)get(sizeof(V4) * Np);
+    lcf_ = (V4*)get(sizeof(V4) * Np);
+    lk_ = (Real*)get(sizeof(Real) * V);
+    ln_ = (V4*)get(sizeof(V4) * V);
+    lc_ = (V4*)get(sizeof(V4) * V);
+    lphi_ = (Real*)get(sizeof(Real) * V);
+    iden_ = (Real*)get(sizeof(Real) * V);
+    idf_ = (double*)get(sizeof(double) * Np);
+    lth_ = (double*)get(sizeof(double) * V);
+    gacc_ = (double4*)get(sizeof(double4) * Np);
+    const int nb = (P.N + BS - 1) / BS;
+    part_ = (double*)get(sizeof(double) * 4 * (size_t)(nb + 1));
+    sums_ = (double*)get(sizeof(double) * 8);
+    ok = ok && lf_[0] && lf_[1] && lr_ && na_ && lcf_ && lk_ && ln_ && lc_ && lphi_ && iden_ && idf_ && lth_ &&
+         gacc_ && part_ && sums_;
+    if (!ok) {
+      E.err_ = "device allocation for the adjoint failed";
+      return CG_ENOMEM;
+    }
+    hipStream_t st = E.stream_;
+    hipError_t e = hipSuccess;
+    auto zero = [&](void* p, size_t b) {
+      if (e == hipSuccess) e = hipMemsetAsync(p, 0, b, st);
+    };
+    zero(lk_, sizeof(Real) * V);
+    zero(ln_, sizeof(V4) * V);
+    zero(lc_, sizeof(V4) * V);
+    zero(lphi_, sizeof(Real) * V);
+    zero(iden_, sizeof(Real) * V);
+    zero(lth_, sizeof(double) * V);
+    zero(gacc_, sizeof(double4) * Np);
+    zero(lr_, sizeof(V2) * Np);
+    zero(sums_, sizeof(double) * 8);
+    if (e != hipSuccess) {
+      E.err_ = hipGetErrorString(e);
+      return CG_EHIP;
+    }
+    if (P.nsb) E.launch(-1, ka_iden<Real, D>, P.nsb, P, E.G_, iden_);
+    E.launch(-1, ka_idf<Real, D>, P.N, P, E.G_, idf_);
+
+    hipEvent_t e0 = event(), e1 = event(), e2 = event();
+    if (!e0 || !e1 || !e2) {
+      E.err_ = "hipEventCreate failed";
+      return CG_EHIP;
+    }
+    (void)hipEventRecord(e0, st);
+    // the state at t = 0 is the engine's own, left untouched
+    Slot cur0;
+    if (kF32) {
+      cur0.a = E.T_[E.cur_];
+      cur0.b = E.AC_[E.cur_];
+    } else {
+      cur0.a = E.fr_[E.cur_];
+      cur0.b = E.fb_[E.cur_];
+    }
+    const bool pre0 = E.pre_;
+    // f(In) on the state at t = cK (c = 0: the engine's state)
+    auto with_ck = [&](int64_t c, auto&& f) {
+      if (c == 0) {
+        if (pre0)
+          f(E.template in_pre<D>());
+        else
+          f(in_of<D>(cur0));
+      } else {
+        f(in_of<D>(ck[(size_t)(c - 1)]));
+      }
+    };
+    // state at t0 + k of the current segment (k = 0: its checkpoint)
+    auto with_seg = [&](int64_t c, int64_t k, auto&& f) {
+      if (k == 0)
+        with_ck(c, f);
+      else
+        f(in_of<D>(ring[(size_t)(k - 1)]));
+    };
+
+    // forward sweep: checkpoints at t = cK; the last segment's states go to the ring
+    const int64_t t_last = (nseg - 1) * K;
+    for (int64_t t = 0; t < T; ++t) {
+      const int64_t t1 = t + 1;
+      Slot out;
+      if (t1 > t_last)
+        out = ring[(size_t)(t1 - t_last - 1)];
+      else if (t1 % K == 0)
+        out = ck[(size_t)(t1 / K - 1)];
+      else
+        out = tmp[(size_t)(t1 & 1)];
+      if (t == 0) {
+        with_ck(0, [&](const auto& in) { fstep<D>(in, out); });
+      } else if (t > t_last) {
+        fstep<D>(in_of<D>(ring[(size_t)(t - t_last - 1)]), out);
+      } else if (t % K == 0) {
+        fstep<D>(in_of<D>(ck[(size_t)(t / K - 1)]), out);
+      } else {
+        fstep<D>(in_of<D>(tmp[(size_t)(t & 1)]), out);
+      }
+    }
+    (void)hipEventRecord(e1, st);
+
+    // terminal condition at t = T
+    with_seg(nseg - 1, Llast, [&](const auto& in) { terminal<D>(in); });
+    // reverse sweep
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      const int64_t L = c == nseg - 1 ? Llast : K;
+      if (c != nseg - 1) {
+        for (int64_t k = 0; k < L; ++k)
+          with_seg(c, k, [&](const auto& in) { fstep<D>(in, ring[(size_t)k]); });
+      }
+      for (int64_t k = L - 1; k >= 0; --k) with_seg(c, k, [&](const auto& in) { rstep<D>(in); });
+    }
+    (void)hipEventRecord(e2, st);
+
+    // parameter gradients
+    E.launch(-1, ka_grad_part<Real, BS>, P.N, P.N, (const double4*)gacc_, part_);
+    hipLaunchKernelGGL(ka_reduce<Real>, dim3(4), dim3(256), 0, st, (const double*)part_, nb, 4, sums_ + 4);
+    if (g->dJ_dtheta_field) {
+      const size_t nbv = (V + 255) / 256;
+      hipLaunchKernelGGL((ka_fill<Real, double>), dim3((unsigned)nbv), dim3(256), 0, st, V, g->dJ_dtheta_field, 0.0);
+      if (P.nsb) E.launch(-1, ka_theta_field<Real, D>, P.nsb, P, E.G_, (const double*)lth_, g->dJ_dtheta_field);
+    }
+    double h[8];
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, sums_, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      E.err_ = hipGetErrorString(e);
+      return CG_EHIP;
+    }
+    float ms1 = 0.f, ms2 = 0.f;
+    (void)hipEventElapsedTime(&ms1, e0, e1);
+    (void)hipEventElapsedTime(&ms2, e1, e2);
+    if (AP_.objective == 0)
+      g->J = h[0] / (h[0] + h[1]);
+    else if (AP_.objective == 1)
+      g->J = h[2];
+    else
+      g->J = h[3];
+    g->dJ_dtheta = h[7];
+    for (int a = 0; a < 3; ++a) g->dJ_dg[a] = a < E.dim_ ? P.rho0 * h[4 + a] : 0.0;
+    g->ms_forward = ms1;
+    g->ms_reverse = ms2;
+    g->work_bytes = (int64_t)bytes_;
+    bool finite = std::isfinite(g->J) && std::isfinite(g->dJ_dtheta);
+    for (int a = 0; a < 3; ++a) finite = finite && std::isfinite(g->dJ_dg[a]);
+    if (!finite) {
+      E.err_ = "non-finite objective or gradient";
+      return CG_EUNSTABLE;
+    }
+    return CG_OK;
+  }
+};
+
+template <class Real>
+int Engine<Real>::adjoint(const cg_adjoint_spec& sp, cg_gradients* g) {
+  AdjointRun<Real> run(*this);
+  return run.run(sp, g);
+}
+
+}  // namespace cg

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <vector>
 
 #include "../../include/cg_lbm.h"
 #include "batch_base.hpp"
@@ -308,6 +309,35 @@ cg_status cg_lbm_set_timing(cg_lbm* h, int mask) {
   if (!h) return fail(CG_EINVAL, "NULL handle");
   h->eng->set_timing(mask);
   return CG_OK;
+}
+
+cg_status cg_lbm_set_wetting(cg_lbm* h, double theta_deg, const double* theta_field_deg) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  if (!theta_field_deg && !(theta_deg > 0.0 && theta_deg < 180.0))
+    return fail(CG_EINVAL, "theta must lie in (0, 180) degrees");
+  std::vector<double> ct = h->S.cos_t, st = h->S.sin_t;
+  std::vector<unsigned> fl = h->S.flags;
+  std::string err;
+  int rc = cg::contact_angles(h->S, theta_deg, theta_field_deg, &ct, &st, &fl, &err);
+  if (rc != CG_OK) return fail((cg_status)rc, err);
+  rc = h->eng->set_angles(ct.data(), st.data(), fl.data());
+  if (rc != CG_OK) return engine_status(h, rc);
+  h->S.cos_t.swap(ct);
+  h->S.sin_t.swap(st);
+  h->S.flags.swap(fl);
+  return CG_OK;
+}
+
+cg_status cg_lbm_set_body_force(cg_lbm* h, const double g[3]) {
+  if (!h || !g) return fail(CG_EINVAL, "NULL argument");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(g[a])) return fail(CG_EINVAL, "g must be finite");
+  return engine_status(h, h->eng->set_body_force(g));
+}
+
+cg_status cg_lbm_adjoint(cg_lbm* h, const cg_adjoint_spec* spec, cg_gradients* out) {
+  if (!h || !spec || !out) return fail(CG_EINVAL, "NULL argument");
+  return engine_status(h, h->eng->adjoint(*spec, out));
 }
 
 cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n) {

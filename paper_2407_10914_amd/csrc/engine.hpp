@@ -26,7 +26,13 @@ namespace cg {
   } while (0)
 
 template <class Real>
+class AdjointRun;
+
+template <class Real>
 class Engine final : public EngineBase {
+  template <class>
+  friend class AdjointRun;
+
   static constexpr bool kF32 = sizeof(Real) == 4;
   static constexpr int BS = 256;
   using V4 = Vec4<Real>;
@@ -284,6 +290,31 @@ class Engine final : public EngineBase {
     return CG_OK;
   }
 
+  int adjoint(const cg_adjoint_spec& sp, cg_gradients* g) override;
+
+  int set_angles(const double* cos_t, const double* sin_t, const unsigned* flags) override {
+    const size_t Np = P_.Np;
+    std::vector<Real> c(Np), s(Np);
+    std::vector<unsigned> vfp(Np);
+    CG_HIP(hipStreamSynchronize(stream_));
+    CG_HIP(hipMemcpy(vfp.data(), G_.vf, sizeof(unsigned) * Np, hipMemcpyDeviceToHost));
+    for (size_t n = 0; n < Np; ++n) {
+      c[n] = (Real)cos_t[n];
+      s[n] = (Real)sin_t[n];
+      vfp[n] = (vfp[n] & kVoxMask) | (flags[n] << kVoxBits);
+    }
+    CG_HIP(hipMemcpy(const_cast<Real*>(G_.cos_t), c.data(), sizeof(Real) * Np, hipMemcpyHostToDevice));
+    CG_HIP(hipMemcpy(const_cast<Real*>(G_.sin_t), s.data(), sizeof(Real) * Np, hipMemcpyHostToDevice));
+    CG_HIP(hipMemcpy(const_cast<unsigned*>(G_.vf), vfp.data(), sizeof(unsigned) * Np, hipMemcpyHostToDevice));
+    return CG_OK;
+  }
+
+  int set_body_force(const double* g) override {
+    CG_HIP(hipStreamSynchronize(stream_));
+    for (int a = 0; a < 3; ++a) P_.rg[a] = a < dim_ ? P_.rho0 * g[a] : 0.0;
+    return CG_OK;
+  }
+
   void set_timing(int mask) override { timing_ = mask; }
   int kernel_times(int64_t* counts, double* ms) override {
     CG_HIP(hipStreamSynchronize(stream_));
@@ -526,3 +557,5 @@ class Engine final : public EngineBase {
 };
 
 }  // namespace cg
+
+#include "adjoint_run.hpp"

@@ -220,7 +220,6 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
 
   // contact angle per fluid boundary point
   const bool field = wet.theta_field_deg != nullptr;
-  const double deg = M_PI / 180.0;
 
   S.nbr.assign((size_t)(Q - 1) * Np, kBounce);
   S.flags.assign(Np, 0u);
@@ -273,24 +272,49 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
         fl |= FL_WET;
         for (int a = 0; a < g.dim; ++a) S.nw[(size_t)a * Np + n] = gr[a] / m;
       }
-      double th;
-      if (!field) {
-        th = wet.theta_deg;
-      } else {
-        double num = 0.0, den = 0.0;
-        for (int i = 1; i < Q; ++i) {
-          const int y = b.link(v, i);
-          if (y < 0 || fluid(y)) continue;
-          num += b.w(i) * wet.theta_field_deg[y];
-          den += b.w(i);
-        }
-        th = num / den;
+      S.fb_node.push_back(n);
+      S.fb_off.push_back((int)S.fb_vox.size());
+      for (int i = 1; i < Q; ++i) {
+        const int y = b.link(v, i);
+        if (y < 0 || fluid(y)) continue;
+        S.fb_vox.push_back(y);
+        S.fb_w.push_back(b.w(i));
       }
-      S.cos_t[n] = std::cos(th * deg);
-      S.sin_t[n] = std::sin(th * deg);
-      if (wet.scheme1_line == CG_S1_LITERAL || th > 90.0) fl |= FL_S1POS;
     }
     S.flags[n] = fl;
+  }
+  S.fb_off.push_back((int)S.fb_vox.size());
+  S.s1_line = wet.scheme1_line;
+  return contact_angles(S, wet.theta_deg, field ? wet.theta_field_deg : nullptr, &S.cos_t, &S.sin_t, &S.flags,
+                        err);
+}
+
+int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
+                   std::vector<double>* sin_t, std::vector<unsigned>* flags, std::string* err) {
+  const double deg = M_PI / 180.0;
+  for (size_t k = 0; k < S.fb_node.size(); ++k) {
+    const int n = S.fb_node[k];
+    double th;
+    if (!theta_field_deg) {
+      th = theta_deg;
+    } else {
+      double num = 0.0, den = 0.0;
+      for (int l = S.fb_off[k]; l < S.fb_off[k + 1]; ++l) {
+        const double t = theta_field_deg[S.fb_vox[l]];
+        if (!(t > 0.0 && t < 180.0)) {
+          *err = "theta field must lie in (0, 180) degrees on solid voxels";
+          return CG_EINVAL;
+        }
+        num += S.fb_w[l] * t;
+        den += S.fb_w[l];
+      }
+      th = num / den;
+    }
+    (*cos_t)[n] = std::cos(th * deg);
+    (*sin_t)[n] = std::sin(th * deg);
+    unsigned& fl = (*flags)[n];
+    fl &= ~FL_S1POS;
+    if (S.s1_line == CG_S1_LITERAL || th > 90.0) fl |= FL_S1POS;
   }
   return CG_OK;
 }

@@ -27,7 +27,19 @@ struct HostSetup {
   std::vector<double> nw;       // [3 * Np]
   std::vector<double> cos_t, sin_t;  // [Np]
   std::vector<double> g3;       // smoothed image [V] (kept for diagnostics)
+  // solid link neighbours of each fluid boundary point, i ascending:
+  // fb_node[k] has links fb_off[k] .. fb_off[k+1]-1 to voxels fb_vox with weights fb_w
+  std::vector<int> fb_node, fb_off, fb_vox;
+  std::vector<double> fb_w;
+  int s1_line = 0;
 };
+
+// Contact angle at every fluid boundary point from the global angle or the
+// per-voxel field (w_i-weighted mean over the solid link neighbours): fills
+// cos_t, sin_t and the FL_S1POS bit of flags for those nodes ([Np] each).
+// Returns CG_OK or CG_EINVAL with *err set.
+int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
+                   std::vector<double>* sin_t, std::vector<unsigned>* flags, std::string* err);
 
 // Returns CG_OK or an error with *err set.
 int build_setup(const cg_geometry& g, const cg_wetting& w, const cg_bc& bc, HostSetup* out, std::string* err);

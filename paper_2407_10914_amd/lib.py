@@ -28,7 +28,9 @@ EXPORTS = ("cg_options_default", "cg_lbm_create", "cg_lbm_destroy", "cg_last_err
            "cg_lbm_get_field", "cg_lbm_info", "cg_lbm_snapshot_bytes", "cg_lbm_save", "cg_lbm_load",
            "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing", "cg_batch_create",
            "cg_batch_destroy", "cg_batch_step", "cg_batch_sync", "cg_batch_set_graph", "cg_batch_tune",
-           "cg_batch_info")
+           "cg_batch_info", "cg_lbm_set_wetting", "cg_lbm_set_body_force", "cg_lbm_adjoint")
+
+OBJECTIVES = {"saturation": 0, "red_volume": 1, "flux": 2}
 
 
 class CgError(RuntimeError):
@@ -80,6 +82,17 @@ class Info(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class AdjointSpec(C.Structure):
+    _fields_ = [("objective", C.c_int), ("axis", C.c_int), ("lo", C.c_int), ("hi", C.c_int),
+                ("n_steps", C.c_int64), ("checkpoint_every", C.c_int64), ("delta", C.c_double)]
+
+
+class Gradients(C.Structure):
+    _fields_ = [("J", C.c_double), ("dJ_dtheta", C.c_double), ("dJ_dg", C.c_double * 3),
+                ("dJ_dtheta_field", C.c_void_p), ("ms_forward", C.c_double), ("ms_reverse", C.c_double),
+                ("work_bytes", C.c_int64)]
+
+
 _LIB = None
 
 
@@ -121,6 +134,9 @@ def load():
     L.cg_lbm_set_timing.argtypes = [p, i]
     L.cg_lbm_kernel_times.argtypes = [p, p, p, p, C.POINTER(C.c_int)]
     L.cg_lbm_reset_timing.argtypes = [p]
+    L.cg_lbm_set_wetting.argtypes = [p, d, p]
+    L.cg_lbm_set_body_force.argtypes = [p, C.POINTER(C.c_double)]
+    L.cg_lbm_adjoint.argtypes = [p, C.POINTER(AdjointSpec), C.POINTER(Gradients)]
     L.cg_batch_create.argtypes = [p, i, C.POINTER(p)]
     L.cg_batch_destroy.argtypes = [p]
     L.cg_batch_destroy.restype = None

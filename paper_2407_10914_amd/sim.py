@@ -171,6 +171,45 @@ class Sim:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         L.check(L.load().cg_lbm_load(self._h, buf.ctypes.data_as(C.c_void_p)))
 
+    # ------------------------------------------------------------ parameters
+    def set_wetting(self, theta_deg=None, theta_field=None):
+        """New contact angle: global (degrees) or a per-voxel field (nz, ny, nx)."""
+        lib = L.load()
+        if theta_field is not None:
+            tf = np.ascontiguousarray(theta_field, dtype=np.float64).reshape(-1)
+            assert tf.size == self._solid.size
+            self._tf = tf
+            L.check(lib.cg_lbm_set_wetting(self._h, 0.0, tf.ctypes.data_as(C.c_void_p)))
+        else:
+            L.check(lib.cg_lbm_set_wetting(self._h, float(theta_deg), None))
+
+    def set_body_force(self, g):
+        L.check(L.load().cg_lbm_set_body_force(self._h, (C.c_double * 3)(*[float(x) for x in g])))
+
+    # --------------------------------------------------------------- adjoint
+    def adjoint(self, objective="saturation", *, n_steps, checkpoint_every=None, axis=2, lo=0, hi=1 << 30,
+                delta=0.0, field_grad=False):
+        """Objective J of the state n_steps ahead and its exact discrete
+        gradient with respect to the contact angle (global, per degree; and,
+        with field_grad, per voxel as a float64 CUDA tensor (nz, ny, nx)) and
+        the body-force acceleration.  The run's state is left unchanged."""
+        torch = _torch()
+        sp = L.AdjointSpec()
+        sp.objective = L.OBJECTIVES[objective] if isinstance(objective, str) else int(objective)
+        sp.axis, sp.lo, sp.hi = int(axis), int(lo), int(hi)
+        sp.n_steps = int(n_steps)
+        sp.checkpoint_every = int(checkpoint_every or n_steps)
+        sp.delta = float(delta)
+        gr = L.Gradients()
+        field = None
+        if field_grad:
+            field = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+            gr.dJ_dtheta_field = field.data_ptr()
+        L.check(L.load().cg_lbm_adjoint(self._h, C.byref(sp), C.byref(gr)))
+        return {"J": gr.J, "dJ_dtheta": gr.dJ_dtheta, "dJ_dg": np.array(gr.dJ_dg[:]),
+                "dJ_dtheta_field": field, "ms_forward": gr.ms_forward, "ms_reverse": gr.ms_reverse,
+                "work_bytes": gr.work_bytes}
+
     # ---------------------------------------------------------------- timing
     KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main")
 

@@ -1,0 +1,185 @@
+"""GPU adjoint (cg_lbm_adjoint) against the oracle's discrete derivative.
+
+The oracle differentiates the same n steps in forward mode on dual numbers;
+the GPU runs the reverse kernels.  For a direction d in parameter space the
+two must agree: <grad J, d> (GPU) = dJ[d] (oracle).  FP64 agrees to rounding;
+FP32 to the tolerance derived in the design notes."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2407_10914_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _sim(solid, prec, **kw):
+    from paper_2407_10914_amd.sim import Sim
+
+    return Sim(solid, precision=prec, **kw)
+
+
+def slug_2d():
+    nx, ny = 24, 10
+    solid = np.zeros((1, ny, nx), np.uint8)
+    solid[0, 0, :] = 1
+    solid[0, -1, :] = 1
+    xx = np.arange(nx)[None, None, :] * np.ones((1, ny, 1))
+    phi0 = np.where((xx >= 6) & (xx < 14), 1.0, -1.0)
+    kw = dict(dim=2, periodic=(1, 0, 0), tau_r=1.0, tau_b=0.8, sigma=0.01, beta=0.7, scheme=1, theta_deg=60.0,
+              collision=0, g=(2e-5, 0, 0))
+    return solid, phi0, kw
+
+
+def tiny_rock(scheme, n=14, nz=20):
+    c = inputs.grf_rock(n=n, nz=nz, corr=3.0, porosity=0.35, seed=77, buffer=3)
+    solid = c.solid
+    zz = np.arange(nz)[:, None, None] * np.ones(solid.shape)
+    phi0 = np.where(zz < 3, 1.0, -1.0)
+    kw = dict(dim=3, periodic=(0, 0, 1), tau_r=1.0, tau_b=0.6, sigma=0.01, beta=0.95, scheme=scheme,
+              theta_deg=40.0, collision=1, g=(0, 0, 1e-4))
+    return solid, phi0, kw
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+OBJ_GPU = {"red_volume": "red_volume", "sat_nw": "saturation", "flux": "flux"}
+
+
+@pytest.mark.parametrize("obj,lo,hi", [("red_volume", 10, 20), ("sat_nw", 10, 20), ("flux", 5, 0)])
+def test_fp64_2d_matches_oracle_tangent(obj, lo, hi):
+    solid, phi0, kw = slug_2d()
+    steps = 40
+    o = O.OracleSim(solid, **kw)
+    J_t, d_theta = o.tangent(phi0, objective=obj, n_steps=steps, seed="theta", axis=0, lo=lo, hi=hi)
+    _, d_gx = o.tangent(phi0, objective=obj, n_steps=steps, seed="gx", axis=0, lo=lo, hi=hi)
+    s = _sim(solid, "f64", **kw)
+    s.set_phase(phi0)
+    r = s.adjoint(OBJ_GPU[obj], n_steps=steps, checkpoint_every=7, axis=0, lo=lo, hi=hi)
+    print(f"{obj}: J {r['J']:.15e} / {J_t:.15e}; dtheta {r['dJ_dtheta']:.12e} / {d_theta:.12e}; "
+          f"dgx {r['dJ_dg'][0]:.12e} / {d_gx:.12e}", flush=True)
+    assert rel(r["J"], J_t) <= 1e-13
+    assert rel(r["dJ_dtheta"], d_theta) <= 1e-9
+    assert rel(r["dJ_dg"][0], d_gx) <= 1e-9
+
+
+def test_checkpoint_interval_does_not_change_the_result():
+    solid, phi0, kw = slug_2d()
+    s = _sim(solid, "f64", **kw)
+    s.set_phase(phi0)
+    t0 = s.time
+    ref = s.observe(axis=0, plane=3)
+    out = [s.adjoint("red_volume", n_steps=30, checkpoint_every=k, axis=0, lo=10, hi=20) for k in (1, 4, 30, 100)]
+    for r in out[1:]:
+        assert r["J"] == out[0]["J"]
+        assert r["dJ_dtheta"] == out[0]["dJ_dtheta"]
+        assert np.array_equal(r["dJ_dg"], out[0]["dJ_dg"])
+    # the run's state is untouched
+    assert s.time == t0
+    after = s.observe(axis=0, plane=3)
+    for k in ("mass_r", "mass_b", "flux_t", "u_max"):
+        assert after[k] == ref[k]
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_fp64_3d_theta_field_matches_oracle_tangent(scheme):
+    solid, phi0, kw = tiny_rock(scheme)
+    nz = solid.shape[0]
+    steps = 30
+    th = np.where(solid == 1, 40.0, 0.0)
+    dirn = np.where(solid == 1, np.random.default_rng(5).standard_normal(solid.shape), 0.0)
+    o = O.OracleSim(solid, theta_field=th, **kw)
+    J_t, d_dir = o.tangent(phi0, objective="sat_nw", n_steps=steps, seed="theta_field", theta_dir=dirn, lo=3,
+                           hi=nz - 3)
+    og = O.OracleSim(solid, **kw)
+    _, d_gz = og.tangent(phi0, objective="sat_nw", n_steps=steps, seed="gz", lo=3, hi=nz - 3)
+    s = _sim(solid, "f64", theta_field=th, **kw)
+    s.set_phase(phi0)
+    r = s.adjoint("saturation", n_steps=steps, checkpoint_every=10, lo=3, hi=nz - 3, field_grad=True)
+    grad = r["dJ_dtheta_field"].cpu().numpy()
+    g_dir = float((grad * dirn).sum())
+    print(f"scheme {scheme}: J {r['J']:.15e} / {J_t:.15e}; <grad,d> {g_dir:.12e} / {d_dir:.12e}; "
+          f"sum grad {grad.sum():.12e} vs dtheta {r['dJ_dtheta']:.12e}", flush=True)
+    assert rel(r["J"], J_t) <= 1e-13
+    assert rel(g_dir, d_dir) <= 1e-9
+    # the field gradient lives on the solid voxels next to the fluid only
+    assert np.all(grad[solid == 0] == 0.0)
+    # a uniform shift of the field is the global-angle derivative
+    assert rel(float(grad.sum()), r["dJ_dtheta"]) <= 1e-10
+    # body force: same geometry with the global angle
+    s2 = _sim(solid, "f64", **kw)
+    s2.set_phase(phi0)
+    r2 = s2.adjoint("saturation", n_steps=steps, checkpoint_every=10, lo=3, hi=nz - 3)
+    print(f"scheme {scheme}: dgz {r2['dJ_dg'][2]:.12e} / {d_gz:.12e}", flush=True)
+    assert rel(r2["dJ_dg"][2], d_gz) <= 1e-9
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_fp32_3d_matches_oracle_tangent(scheme):
+    solid, phi0, kw = tiny_rock(scheme)
+    nz = solid.shape[0]
+    steps = 30
+    o = O.OracleSim(solid, eps="f32", **kw)
+    J_t, d_theta = o.tangent(phi0, objective="sat_nw", n_steps=steps, seed="theta", lo=3, hi=nz - 3)
+    _, d_gz = o.tangent(phi0, objective="sat_nw", n_steps=steps, seed="gz", lo=3, hi=nz - 3)
+    s = _sim(solid, "f32", **kw)
+    s.set_phase(phi0)
+    r = s.adjoint("saturation", n_steps=steps, checkpoint_every=10, lo=3, hi=nz - 3)
+    e = (rel(r["J"], J_t), rel(r["dJ_dtheta"], d_theta), rel(r["dJ_dg"][2], d_gz))
+    print(f"fp32 scheme {scheme}: J {r['J']:.9e}/{J_t:.9e} dtheta {r['dJ_dtheta']:.6e}/{d_theta:.6e} "
+          f"dgz {r['dJ_dg'][2]:.6e}/{d_gz:.6e} rel {e}", flush=True)
+    assert e[0] <= 1e-6
+    assert e[1] <= 2e-3 and e[2] <= 2e-3
+
+
+def test_autograd_function_hands_out_the_adjoint_gradient():
+    from paper_2407_10914_amd.autograd import objective
+
+    solid, phi0, kw = slug_2d()
+    s = _sim(solid, "f64", **kw)
+    theta = torch.tensor(60.0, dtype=torch.float64, requires_grad=True)
+    g = torch.tensor([2e-5, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    J = objective(s, phi0, objective="red_volume", n_steps=25, checkpoint_every=5, axis=0, lo=10, hi=20,
+                  theta=theta, g=g)
+    (3.0 * J).backward()
+    s.set_phase(phi0)
+    r = s.adjoint("red_volume", n_steps=25, axis=0, lo=10, hi=20)
+    assert float(J) == r["J"]
+    assert float(theta.grad) == 3.0 * r["dJ_dtheta"]
+    assert float(g.grad[0]) == 3.0 * r["dJ_dg"][0]
+    # central differences of the GPU forward runs themselves
+    def Jat(th):
+        with torch.no_grad():
+            return float(objective(s, phi0, objective="red_volume", n_steps=25, axis=0, lo=10, hi=20,
+                                   theta=torch.tensor(th, dtype=torch.float64), g=g.detach()))
+    h = 1e-3
+    fd = (Jat(60.0 + h) - Jat(60.0 - h)) / (2 * h)
+    print(f"autograd: dtheta {r['dJ_dtheta']:.12e} fd {fd:.12e}", flush=True)
+    assert rel(r["dJ_dtheta"], fd) <= 1e-5
+
+
+def test_regularised_normal_jacobian_runs_and_stays_close():
+    solid, phi0, kw = tiny_rock(1)
+    nz = solid.shape[0]
+    s = _sim(solid, "f64", **kw)
+    s.set_phase(phi0)
+    exact = s.adjoint("saturation", n_steps=10, lo=3, hi=nz - 3)
+    reg = s.adjoint("saturation", n_steps=10, lo=3, hi=nz - 3, delta=1e-3)
+    assert reg["J"] == exact["J"]
+    assert np.isfinite(reg["dJ_dtheta"]) and np.all(np.isfinite(reg["dJ_dg"]))
+    assert rel(reg["dJ_dtheta"], exact["dJ_dtheta"]) < 0.5
+
+
+def test_zou_he_runs_are_rejected():
+    from paper_2407_10914_amd.lib import CgError
+
+    c = inputs.tube(nz=12, radius=4.0, nx=12, ny=12, wet_len=4)
+    s = _sim(c.solid, "f64", dim=3, periodic=c.periodic, bc=1, rho_in=1.01, rho_out=1.0, scheme=1,
+             theta_deg=45.0, tau_r=1.0, tau_b=1.0, sigma=0.02, beta=0.9)
+    s.set_phase(c.phi0)
+    with pytest.raises(CgError):
+        s.adjoint("saturation", n_steps=2)
