@@ -148,6 +148,58 @@ def batched_leg(steps, warmup, count=64, ref_edge=256):
             "ratio": round(batched / single, 4), "tuning": report}
 
 
+def adjoint_leg(n_steps=2000, K=100, n=128):
+    """Adjoint through drainage: the 128^3 Gaussian-random-field rock (porosity
+    0.22, z periodic, non-wetting fluid in the inlet buffer, body force 1e-5
+    along z), a per-voxel contact-angle field of 40 deg on the solid, FP32
+    MRT Scheme-I; objective = non-wetting mass saturation of the rock region
+    after n_steps; checkpoints every K steps.  The forward step time is taken
+    on the same run by plain stepping."""
+    import torch
+
+    from paper_2407_10914_amd import inputs
+    from paper_2407_10914_amd.sim import Sim
+
+    case, th = inputs.drainage_rock(n=n)
+    nz = case.solid.shape[0]
+    buf = case.meta["buffer"]
+    kw = dict(dim=3, periodic=case.periodic, tau_r=1.0, tau_b=0.6, sigma=0.01, beta=0.95, scheme=1,
+              theta_deg=40.0, collision=1, g=(0.0, 0.0, 1e-5))
+    sim = Sim(case.solid, precision="f32", theta_field=th, **kw)
+    n_fluid = sim.info()["fluid"]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sim.set_phase(case.phi0)
+    sim.step(20)
+    sim.sync()
+    sim.set_phase(case.phi0)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(n_steps)
+    e1.record(stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / n_steps
+    sim.set_phase(case.phi0)
+    sim.adjoint("saturation", n_steps=4, checkpoint_every=2, lo=buf, hi=nz - buf, field_grad=True)  # warm-up
+    t0 = time.perf_counter()
+    r = sim.adjoint("saturation", n_steps=n_steps, checkpoint_every=K, lo=buf, hi=nz - buf, field_grad=True)
+    wall = time.perf_counter() - t0
+    gf = r["dJ_dtheta_field"]
+    out = {"workload": f"{n}^3 drainage rock, FP32 MRT Scheme-I, theta(x) = 40 deg, g_z = 1e-5, "
+                       f"objective S_nw (rock region) after {n_steps} steps, checkpoint every {K}",
+           "fluid_nodes": int(n_fluid), "steps": n_steps, "K": K, "J": r["J"], "dJ_dtheta": r["dJ_dtheta"],
+           "dJ_dgz": float(r["dJ_dg"][2]), "dJ_dtheta_field_l2": float(gf.norm()),
+           "forward_ms_per_step": round(fwd_ms, 5), "adjoint_forward_sweep_ms": round(r["ms_forward"], 2),
+           "adjoint_reverse_ms": round(r["ms_reverse"], 2),
+           "ratio_reverse_to_forward": round(r["ms_reverse"] / (n_steps * fwd_ms), 4),
+           "ratio_total_to_forward": round((r["ms_forward"] + r["ms_reverse"]) / (n_steps * fwd_ms), 4),
+           "wall_s": round(wall, 3), "work_gb": round(r["work_bytes"] / 1e9, 3)}
+    del gf, r, sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +209,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-k", type=int, default=100)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -223,6 +278,10 @@ def main():
     batched = None
     if not args.no_batch:
         batched = batched_leg(args.batch_steps, max(2, args.warmup // 4))
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_leg(args.adjoint_steps, args.adjoint_k)
+        print(f"# adjoint: {adj}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(case, kw)
@@ -243,7 +302,7 @@ def main():
                                "porosity 0.22, Zou-He drho=0.02, Scheme-I 30 deg, MRT, FP32",
                    "fluid_nodes": n_fluid, "voxels": info["voxels"], "voxel_mlups": round(vox_mlups, 1),
                    "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3),
-                   "sat_nw_mass": obs["sat_nw_mass"], "batched": batched},
+                   "sat_nw_mass": obs["sat_nw_mass"], "batched": batched, "adjoint": adj},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -41,54 +41,77 @@ namespace cg {
 // ------------------------------------------------------- forward-mode lanes
 // A value with four directional derivatives.  Branches compare values only,
 // so the lanes are the derivative of the branch the value takes.
+template <class S>
 struct Tan4 {
-  double v;
-  double d[4];
-  __device__ __forceinline__ Tan4() : v(0.0), d{0.0, 0.0, 0.0, 0.0} {}
-  __device__ __forceinline__ Tan4(double a) : v(a), d{0.0, 0.0, 0.0, 0.0} {}
+  S v;
+  S d[4];
+  __device__ __forceinline__ Tan4() : v(S(0)), d{S(0), S(0), S(0), S(0)} {}
+  __device__ __forceinline__ Tan4(double a) : v(S(a)), d{S(0), S(0), S(0), S(0)} {}
 };
-__device__ __forceinline__ Tan4 operator+(const Tan4& a, const Tan4& b) {
-  Tan4 r(a.v + b.v);
+template <class S>
+__device__ __forceinline__ Tan4<S> operator+(const Tan4<S>& a, const Tan4<S>& b) {
+  Tan4<S> r;
+  r.v = a.v + b.v;
 #pragma unroll
   for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] + b.d[k];
   return r;
 }
-__device__ __forceinline__ Tan4 operator-(const Tan4& a, const Tan4& b) {
-  Tan4 r(a.v - b.v);
+template <class S>
+__device__ __forceinline__ Tan4<S> operator-(const Tan4<S>& a, const Tan4<S>& b) {
+  Tan4<S> r;
+  r.v = a.v - b.v;
 #pragma unroll
   for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] - b.d[k];
   return r;
 }
-__device__ __forceinline__ Tan4 operator-(const Tan4& a) {
-  Tan4 r(-a.v);
+template <class S>
+__device__ __forceinline__ Tan4<S> operator-(const Tan4<S>& a) {
+  Tan4<S> r;
+  r.v = -a.v;
 #pragma unroll
   for (int k = 0; k < 4; ++k) r.d[k] = -a.d[k];
   return r;
 }
-__device__ __forceinline__ Tan4 operator*(const Tan4& a, const Tan4& b) {
-  Tan4 r(a.v * b.v);
+template <class S>
+__device__ __forceinline__ Tan4<S> operator*(const Tan4<S>& a, const Tan4<S>& b) {
+  Tan4<S> r;
+  r.v = a.v * b.v;
 #pragma unroll
   for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
   return r;
 }
-__device__ __forceinline__ Tan4 operator/(const Tan4& a, const Tan4& b) {
-  const double q = a.v / b.v;
-  Tan4 r(q);
+template <class S>
+__device__ __forceinline__ Tan4<S> operator/(const Tan4<S>& a, const Tan4<S>& b) {
+  const S q = a.v / b.v;
+  const S ib = S(1) / b.v;
+  Tan4<S> r;
+  r.v = q;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r.d[k] = (a.d[k] - q * b.d[k]) / b.v;
+  for (int k = 0; k < 4; ++k) r.d[k] = (a.d[k] - q * b.d[k]) * ib;
   return r;
 }
-__device__ __forceinline__ bool operator<=(const Tan4& a, const Tan4& b) { return a.v <= b.v; }
-__device__ __forceinline__ bool operator<(const Tan4& a, const Tan4& b) { return a.v < b.v; }
-__device__ __forceinline__ Tan4 sqrt(const Tan4& a) {
-  const double s = ::sqrt(a.v);
-  Tan4 r(s);
-  const double h = s > 0.0 ? 0.5 / s : 0.0;
+template <class S>
+__device__ __forceinline__ bool operator<=(const Tan4<S>& a, const Tan4<S>& b) {
+  return a.v <= b.v;
+}
+template <class S>
+__device__ __forceinline__ bool operator<(const Tan4<S>& a, const Tan4<S>& b) {
+  return a.v < b.v;
+}
+template <class S>
+__device__ __forceinline__ Tan4<S> sqrt(const Tan4<S>& a) {
+  const S s = ::sqrt(a.v);
+  Tan4<S> r;
+  r.v = s;
+  const S h = s > S(0) ? S(0.5) / s : S(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) r.d[k] = a.d[k] * h;
   return r;
 }
-__device__ __forceinline__ Tan4 fabs(const Tan4& a) { return a.v < 0.0 ? -a : a; }
+template <class S>
+__device__ __forceinline__ Tan4<S> fabs(const Tan4<S>& a) {
+  return a.v < S(0) ? -a : a;
+}
 
 // --------------------------------------------------------------- buffers
 template <class Real>
@@ -123,7 +146,7 @@ struct AdjBufs {
   Real* lphi;          // [V] lambda phi / (sum of link weights) at solid boundary points, 0 elsewhere
   const Real* iden;    // [V] 1 / (sum of fluid-link weights) at solid boundary points, 0 elsewhere
   const double* idf;   // [Np] 1 / (sum of solid-link weights) at fluid boundary points, 0 elsewhere
-  double4* gacc;       // [Np] sum over steps of lambda F (xyz) and lambda theta (w, per degree)
+  double* pacc;        // [blocks][4] per-block sums over steps of lambda F (xyz) and lambda theta (per degree)
   double* lth;         // [V] sum over steps of lambda theta * idf at fluid boundary voxels
 };
 
@@ -163,72 +186,89 @@ __device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G
 }
 
 // ------------------------------------------------------------------ ka_node
-// kSeed: no lambda_{t+1}; instead the plane-flux objective J = sum (j + F/2)_axis
-// is seeded at the plane nodes (the terminal condition of objective 2).
-template <class Real, int D, bool kSeed, class In>
+// Streaming form, three passes over the directions so that few per-direction
+// values stay live:
+//   pass 1  gather (delta_i, mu_i) = (lambda c^r_i - lambda c^b_i,
+//           lambda c^b_i + a delta_i) of the post-collision populations, form
+//           y_i = f_i - f^eq_i + Fbar_i/2 and accumulate the moments M y,
+//           M delta, M mu and the recolouring adjoints;
+//   between lambda a = sum_i f''_i delta_i with f'' = f + Fbar - M^-1 S M y
+//           (BGK: M = I, S = S_nu), the rate adjoints lambda S_k = -(M mu)_k (M y)_k / |M_k|^2;
+//   pass 2  lambda y_i = -(M^T S M^-T mu)_i, lambda f_i = mu_i + lambda y_i,
+//           lambda f^eq_i = -lambda y_i, lambda Fbar_i = mu_i + lambda y_i / 2
+//           and their contributions to lambda rho, lambda u, lambda F;
+//   pass 3  lambda f_i += e_i . lambda j (velocity, Eq. 22), store L.
+// kSeed: no lambda_{t+1}; the plane-flux objective J = sum (j + F/2)_axis is
+// seeded at the plane nodes instead (terminal condition of objective 2).
+// lF receives this node's lambda F (summed per block by the caller).
+template <class Real, int D, bool kSeed, bool kMrt, class In>
 __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
-                                           const In& in, const AdjBufs<Real>& A, const AdjParams& AP, int n) {
+                                           const In& in, const AdjBufs<Real>& A, const AdjParams& AP, int n,
+                                           double* lFout) {
+  static_assert(D == 3 || !kMrt, "MRT is defined for D3Q19");
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = Real;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
-  // reverse streaming: c_j(x) became f_j(x + e_j) when that voxel is fluid,
-  // else f_opp(j)(x) (halfway bounce-back)
-  CT lcr[Q], lcb[Q];
-  if constexpr (kSeed) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      lcr[i] = CT(0);
-      lcb[i] = CT(0);
-    }
-  } else {
-    const Vec2<Real> own = A.lr[n];
-    unroll<Q>([&](auto J) {
-      constexpr int j = J;
-      if constexpr (j == 0) {
-        const CT l = A.lf_in[n];
-        lcr[0] = l + own.x;
-        lcb[0] = l + own.y;
-      } else {
-        constexpr int o = opp<D>(j);
-        const int s = G.nbr[(o - 1) * P.Np + n];  // node at x - e_o = x + e_j
-        CT l;
-        Vec2<Real> r;
-        if (s >= 0) {
-          l = A.lf_in[j * P.Np + s];
-          r = A.lr[s];
-        } else {
-          l = A.lf_in[o * P.Np + n];
-          r = own;
-        }
-        lcr[j] = l + r.x;
-        lcb[j] = l + r.y;
-      }
-    });
-  }
-  // forward quantities of the step at t
-  Real fr[Q], fx[Q];
-  Real rr, rb, rho;
-  adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
   const CT rho0 = (CT)P.rho0;
-  CT drho;  // density handed to the equilibrium (deviation for the compact state)
+  // state at t: x_i = f^t_i (canonical) or g_i = f^t_i - w_i rho0 (compact).
+  // The compact state needs only the totals here: rho^r follows from the
+  // phase field k_phase computed from the same state, rho^r = rho (1 + phi)/2.
+  CT x[Q];
+  CT rr, rb, rho, drho;
   if constexpr (kDev) {
-    CT s = fx[0];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) s = s + fx[i];
-    drho = s;
+    if constexpr (In::kPull) {
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i == 0) {
+          x[0] = (CT)in.T[n];
+        } else {
+          const int s = G.nbr[(i - 1) * P.Np + n];
+          x[i] = (CT)(s >= 0 ? in.T[i * P.Np + s] : in.T[opp<D>(i) * P.Np + n]);
+        }
+      });
+    } else {
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        CT r, g;
+        in.template get<i>(n, r, g);
+        x[i] = g;
+      });
+    }
+    CT t = (CT)Lat<D>::w(0) * rho0 + x[0];
+    CT sg = x[0];
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      t = t + ((CT)Lat<D>::w(i) * rho0 + x[i]);
+      sg = sg + x[i];
+    });
+    rho = t;
+    drho = sg;
+    rr = rho * (CT(1) + (CT)R.phi[v]) * CT(0.5);
+    rb = rho - rr;
   } else {
+    Real fr[Q], fx[Q];
+    load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+    CT a = fr[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) a = a + (CT)fr[i];
+    CT b = fx[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) b = b + (CT)fx[i];
+    rr = a;
+    rb = b;
+    rho = a + b;
     drho = rho;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = (CT)fr[i] + (CT)fx[i];
   }
   const CT rho_u = kDev ? rho0 + drho : rho;
   const Vec4<Real> f4 = R.f[n];
   const Vec4<Real> n4 = R.n[v];
-  const Vec4<Real> c4 = R.c[n];
   const CT F[3] = {(CT)f4.x, (CT)f4.y, (CT)f4.z};
   const CT kap = (CT)f4.w;
   const CT nv[3] = {(CT)n4.x, (CT)n4.y, (CT)n4.z};
-  const CT Cv[3] = {(CT)c4.x, (CT)c4.y, (CT)c4.z};
   const CT phi = (CT)R.phi[v];
   CT u[3] = {CT(0), CT(0), CT(0)};
   unroll<D>([&](auto A_) {
@@ -237,9 +277,8 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     unroll<Q>([&](auto I) {
       constexpr int i = I;
       constexpr int e = Lat<D>::e(i, a);
-      const CT ft_i = kDev ? (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
-      if constexpr (e == 1) j = j + ft_i;
-      if constexpr (e == -1) j = j - ft_i;
+      if constexpr (e == 1) j = j + x[i];
+      if constexpr (e == -1) j = j - x[i];
     });
     u[a] = (j + CT(0.5) * F[a]) / rho_u;
   });
@@ -247,95 +286,122 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   if constexpr (D == 3) usq = usq + u[2] * u[2];
   CT s_nu, s_q;
   rates(P, phi, s_nu, s_q);
-  // y = f - f^eq + Fbar/2 and Fbar
-  CT y[Q], gu[Q];
-  unroll<Q>([&](auto I) {
-    constexpr int i = I;
-    const CT fe = eq_i<D, i>(drho, rho0, u, usq);
-    gu[i] = guo_i<D, i>(u, F);
-    const CT base = kDev ? (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
-    y[i] = base - fe + CT(0.5) * gu[i];
-  });
-  const CT ra = (CT)rr / (CT)rho;
-  const CT rbb = (CT)rr * (CT)rb / (CT)rho;
-  // reverse of recolouring, Eqs. (20)-(21): c^r = a f'' + beta w b e.n, c^b = f'' - c^r
-  CT dl[Q], mu[Q];
+  const CT ra = rr / rho;
+  const CT rbb = rr * rb / rho;
+
+  // ---- pass 1
+  CT mu[Q];
+  CT a1 = CT(0), lb = CT(0), lnr[3] = {CT(0), CT(0), CT(0)};
+  CT my[19], md[19], nu[19];  // moments of y, delta, mu (non-conserved rows; BGK uses slot 0)
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    dl[i] = lcr[i] - lcb[i];
-    mu[i] = lcb[i] + ra * dl[i];
+  for (int k = 0; k < 19; ++k) {
+    my[k] = CT(0);
+    md[k] = CT(0);
+    nu[k] = CT(0);
   }
-  // collision f'' = f + Fbar - M^-1 S M y (BGK: M = I, S = s_nu); post-collision
-  // totals, lambda y and the rate adjoints
-  CT ly[Q], la = CT(0), lsnu = CT(0), lsq = CT(0);
-  auto bgk = [&]() {
-    unroll<Q>([&](auto I) {
-      constexpr int i = I;
-      const CT base = kDev ? (CT)Lat<D>::w(i) * rho0 + (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
-      const CT out = base + gu[i] - s_nu * y[i];
-      la = la + out * dl[i];
-      lsnu = lsnu - mu[i] * y[i];
-      ly[i] = -s_nu * mu[i];
-    });
-  };
-  if constexpr (D == 3) {
-    if (P.collision == 1) {
-      CT my[19], nu[19];
-      unroll<19>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (rate_class(k) != 0) {
-          CT a = CT(0), b = CT(0);
-          unroll<19>([&](auto I) {
-            constexpr int i = I;
-            constexpr int m = Mkj(k, i);
-            if constexpr (m != 0) {
-              a = a + (CT)m * y[i];
-              b = b + (CT)m * mu[i];
-            }
-          });
-          constexpr CT inorm = (CT)(1.0 / (double)Mnorm2(k));
-          const CT S = rate_class(k) == 1 ? s_nu : s_q;
-          // lambda S_k = -(M^-T mu)_k (M y)_k
-          if constexpr (rate_class(k) == 1)
-            lsnu = lsnu - b * inorm * a;
-          else
-            lsq = lsq - b * inorm * a;
-          my[k] = S * a * inorm;
-          nu[k] = S * b * inorm;
-        }
-      });
-      unroll<19>([&](auto I) {
-        constexpr int i = I;
-        CT s = CT(0), t = CT(0);
-        unroll<19>([&](auto K) {
-          constexpr int k = K;
-          constexpr int m = Mkj(k, i);
-          if constexpr (rate_class(k) != 0 && m != 0) {
-            s = s + (CT)m * my[k];
-            t = t + (CT)m * nu[k];
-          }
-        });
-        const CT base = kDev ? (CT)Lat<D>::w(i) * rho0 + (CT)fx[i] : (CT)fr[i] + (CT)fx[i];
-        const CT out = base + gu[i] - s;
-        la = la + out * dl[i];
-        ly[i] = -t;
-      });
-    } else {
-      bgk();
-    }
-  } else {
-    bgk();
-  }
-  // lambda of f (total), f^eq and Fbar
-  CT lft[Q];
-  CT lrho = CT(0), lu[3] = {CT(0), CT(0), CT(0)}, lF[3] = {CT(0), CT(0), CT(0)};
-  CT lb = CT(0), lnr[3] = {CT(0), CT(0), CT(0)};
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     constexpr double w = Lat<D>::w(i);
-    lft[i] = mu[i] + ly[i];
-    const CT lfe = -ly[i];
-    const CT lgu = mu[i] + CT(0.5) * ly[i];
+    // reverse streaming: c_i(x) became f_i(x + e_i) when that voxel is fluid,
+    // else f_opp(i)(x) (halfway bounce-back)
+    CT dl = CT(0), m = CT(0);
+    if constexpr (!kSeed) {
+      int li, ri;
+      if constexpr (i == 0) {
+        li = n;
+        ri = n;
+      } else {
+        constexpr int o = opp<D>(i);
+        const int s = G.nbr[(o - 1) * P.Np + n];  // node at x - e_o = x + e_i
+        li = s >= 0 ? i * P.Np + s : o * P.Np + n;
+        ri = s >= 0 ? s : n;
+      }
+      const CT l = A.lf_in[li];
+      const Vec2<Real> r = A.lr[ri];
+      dl = (CT)r.x - (CT)r.y;
+      m = l + (CT)r.y + ra * dl;
+    }
+    const CT fe = eq_i<D, i>(drho, rho0, u, usq);
+    const CT gu = guo_i<D, i>(u, F);
+    const CT y = x[i] - fe + CT(0.5) * gu;
+    const CT base = kDev ? (CT)w * rho0 + x[i] : x[i];
+    a1 = a1 + (base + gu) * dl;
+    if constexpr (kMrt) {
+      unroll<19>([&](auto K) {
+        constexpr int k = K;
+        constexpr int mk = Mkj(k, i);
+        if constexpr (rate_class(k) != 0 && mk != 0) {
+          my[k] = my[k] + (CT)mk * y;
+          md[k] = md[k] + (CT)mk * dl;
+          nu[k] = nu[k] + (CT)mk * m;
+        }
+      });
+    } else {
+      md[0] = md[0] + y * dl;
+      my[0] = my[0] + m * y;
+    }
+    mu[i] = m;
+    if constexpr (i > 0) {
+      CT en = CT(0);
+      unroll<D>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<D>::e(i, a);
+        if constexpr (e == 1) en = en + nv[a];
+        if constexpr (e == -1) en = en - nv[a];
+      });
+      const CT q = (CT)(P.beta * w) * dl;
+      lb = lb + q * en;
+      unroll<D>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<D>::e(i, a);
+        if constexpr (e == 1) lnr[a] = lnr[a] + q;
+        if constexpr (e == -1) lnr[a] = lnr[a] - q;
+      });
+    }
+  });
+  // ---- lambda a and the rate adjoints
+  CT la, lsnu = CT(0), lsq = CT(0);
+  if constexpr (kMrt) {
+    la = a1;
+    {
+      unroll<19>([&](auto K) {
+        constexpr int k = K;
+        constexpr int rc = rate_class(k);
+        if constexpr (rc != 0) {
+          constexpr CT inorm = (CT)(1.0 / (double)Mnorm2(k));
+          const CT S = rc == 1 ? s_nu : s_q;
+          la = la - S * inorm * my[k] * md[k];
+          if constexpr (rc == 1)
+            lsnu = lsnu - nu[k] * inorm * my[k];
+          else
+            lsq = lsq - nu[k] * inorm * my[k];
+          nu[k] = S * inorm * nu[k];
+        }
+      });
+    }
+  } else {
+    la = a1 - s_nu * md[0];
+    lsnu = -my[0];
+  }
+  // ---- pass 2
+  CT lrho = CT(0), lu[3] = {CT(0), CT(0), CT(0)}, lF[3] = {CT(0), CT(0), CT(0)};
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    constexpr double w = Lat<D>::w(i);
+    CT ly;
+    if constexpr (kMrt) {
+      CT t = CT(0);
+      unroll<19>([&](auto K) {
+        constexpr int k = K;
+        constexpr int mk = Mkj(k, i);
+        if constexpr (rate_class(k) != 0 && mk != 0) t = t + (CT)mk * nu[k];
+      });
+      ly = -t;
+    } else {
+      ly = -s_nu * mu[i];
+    }
+    const CT lfe = -ly;
+    const CT lgu = mu[i] + CT(0.5) * ly;
     CT eu = CT(0), eF = CT(0);
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
@@ -360,26 +426,8 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
       lu[a] = lu[a] + qe * (CT(3) * e + CT(9) * eu * e - CT(3) * u[a]) + qg * (CT(-3) * F[a] + CT(9) * eF * e);
       lF[a] = lF[a] + qg * (CT(3) * (e - u[a]) + CT(9) * eu * e);
     });
-    if constexpr (i > 0) {
-      CT en = CT(0);
-      unroll<D>([&](auto A_) {
-        constexpr int a = A_;
-        constexpr int e = Lat<D>::e(i, a);
-        if constexpr (e == 1) en = en + nv[a];
-        if constexpr (e == -1) en = en - nv[a];
-      });
-      const CT q = (CT)(P.beta * w) * dl[i];
-      lb = lb + q * en;
-      unroll<D>([&](auto A_) {
-        constexpr int a = A_;
-        constexpr int e = Lat<D>::e(i, a);
-        if constexpr (e == 1) lnr[a] = lnr[a] + q;
-        if constexpr (e == -1) lnr[a] = lnr[a] - q;
-      });
-    }
+    mu[i] = mu[i] + ly;  // lambda f_i (total) before the velocity term
   });
-#pragma unroll
-  for (int a = 0; a < D; ++a) lnr[a] = lnr[a] * rbb;
   // rates, Eqs. (13)-(16): S_nu(phi), S_q(S_nu)
   {
     const CT inv_nu = (CT(1) + phi) / (CT(2) * (CT)P.nu_r) + (CT(1) - phi) / (CT(2) * (CT)P.nu_b);
@@ -387,8 +435,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     const CT dinv = CT(1) / (CT(2) * (CT)P.nu_r) - CT(1) / (CT(2) * (CT)P.nu_b);
     const CT dsdphi = CT(3) * s_nu * s_nu * nuv * nuv * dinv;
     const CT dq = CT(-48) / ((CT(8) - s_nu) * (CT(8) - s_nu));
-    lsnu = lsnu + lsq * dq;
-    lsnu = lsnu * dsdphi;  // now lambda phi (node part)
+    lsnu = (lsnu + lsq * dq) * dsdphi;  // now lambda phi (node part)
   }
   // velocity, Eq. (22): u = (j + F/2) / rho
   CT lj[3] = {CT(0), CT(0), CT(0)};
@@ -400,67 +447,85 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   }
   if constexpr (kSeed) {
     if (coord_of(P, v, AP.axis) == AP.lo) {
-      lj[AP.axis] = lj[AP.axis] + CT(1);
-      lF[AP.axis] = lF[AP.axis] + CT(0.5);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (a == AP.axis) {
+          lj[a] = lj[a] + CT(1);
+          lF[a] = lF[a] + CT(0.5);
+        }
     }
   }
+  // ---- pass 3: store L
   unroll<Q>([&](auto I) {
     constexpr int i = I;
+    CT t = mu[i];
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
       constexpr int e = Lat<D>::e(i, a);
-      if constexpr (e == 1) lft[i] = lft[i] + lj[a];
-      if constexpr (e == -1) lft[i] = lft[i] - lj[a];
+      if constexpr (e == 1) t = t + lj[a];
+      if constexpr (e == -1) t = t - lj[a];
     });
+    A.lf_out[i * P.Np + n] = t;
   });
-  // recolouring fractions a = rho^r/rho, b = rho^r rho^b / rho
-  const CT irho = CT(1) / (CT)rho;
-  CT lrr = la * irho + lb * (CT)rb * irho;
-  CT lrb = lb * (CT)rr * irho;
+  // recolouring fractions a = rho^r/rho, b = rho^r rho^b / rho; rho = rho^r + rho^b
+  const CT irho = CT(1) / rho;
+  CT lrr = la * irho + lb * rb * irho;
+  CT lrb = lb * rr * irho;
   lrho = lrho - (la * ra + lb * rbb) * irho;
   lrr = lrr + lrho;
   lrb = lrb + lrho;
   // phi = (rho^r - rho^b) / rho
-  const CT dr = CT(2) * (CT)rb * irho * irho;
-  const CT db = CT(-2) * (CT)rr * irho * irho;
-  // force F = sigma/2 kappa C + rho0 g
-  CT lkap = CT(0);
-#pragma unroll
-  for (int a = 0; a < D; ++a) lkap = lkap + lF[a] * Cv[a];
-  lkap = lkap * (CT)P.half_sigma;
-  const CT hk = (CT)P.half_sigma * kap;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) A.lf_out[i * P.Np + n] = lft[i];
+  const CT dr = CT(2) * rb * irho * irho;
+  const CT db = CT(-2) * rr * irho * irho;
   Vec4<Real> na;
   na.x = lrr + lsnu * dr;
   na.y = lrb + lsnu * db;
   na.z = dr;
   na.w = db;
   A.na[n] = na;
+  // force F = sigma/2 kappa C + rho0 g
+  const Vec4<Real> c4 = R.c[n];
+  const CT Cv[3] = {(CT)c4.x, (CT)c4.y, (CT)c4.z};
+  CT lkap = CT(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) lkap = lkap + lF[a] * Cv[a];
+  A.lk[v] = lkap * (CT)P.half_sigma;
+  const CT hk = (CT)P.half_sigma * kap;
   Vec4<Real> q;
   q.x = hk * lF[0];
   q.y = hk * lF[1];
   q.z = D == 3 ? hk * lF[2] : Real(0);
   q.w = Real(0);
   A.lcf[n] = q;
-  A.lk[v] = lkap;
   Vec4<Real> l4;
-  l4.x = lnr[0];
-  l4.y = lnr[1];
-  l4.z = D == 3 ? lnr[2] : Real(0);
+  l4.x = lnr[0] * rbb;
+  l4.y = lnr[1] * rbb;
+  l4.z = D == 3 ? lnr[2] * rbb : Real(0);
   l4.w = Real(0);
   A.ln[v] = l4;
-  double4 g = A.gacc[n];
-  g.x += (double)lF[0];
-  g.y += (double)lF[1];
-  if constexpr (D == 3) g.z += (double)lF[2];
-  A.gacc[n] = g;
+#pragma unroll
+  for (int a = 0; a < D; ++a) lFout[a] = (double)lF[a];
 }
 
-template <class Real, int D, bool kSeed, class In>
-__global__ void __launch_bounds__(256) ka_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A, AdjParams AP) {
+// Per-block sums of this step's parameter adjoints, added to the block's own
+// accumulator row (same block -> same tile every launch: deterministic).
+template <int BS, int NC>
+__device__ __forceinline__ void block_accumulate(const double* vals, int col0, double* pacc) {
+  __shared__ double sh[BS / 64];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double t = block_sum<BS>(vals[c], sh);
+    if (threadIdx.x == 0) pacc[blockIdx.x * 4 + col0 + c] += t;
+  }
+}
+
+template <class Real, int D, bool kSeed, bool kMrt, class In>
+__global__ void __launch_bounds__(256) ka_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A,
+                                               AdjParams AP) {
   const int n = node_id();
-  if (n < P.N) d_adj_node<Real, D, kSeed, In>(P, G, R, in, A, AP, n);
+  double lF[3] = {0.0, 0.0, 0.0};
+  if (n < P.N) d_adj_node<Real, D, kSeed, kMrt, In>(P, G, R, in, A, AP, n, lF);
+  block_accumulate<256, 3>(lF, 0, A.pacc);
 }
 
 // ------------------------------------------------------------------ ka_curv
@@ -546,6 +611,8 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
   A.ln[v] = o;
 }
 
+// Separate launches for the fluid nodes and the solid boundary points, so
+// that each XCD works on a contiguous range of either list.
 template <class Real, int D, bool kSb>
 __global__ void ka_curv(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A) {
   d_adj_curv<Real, D, kSb>(P, G, R, A, node_id());
@@ -554,9 +621,10 @@ __global__ void ka_curv(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> 
 // ---------------------------------------------------------------- ka_normal
 template <class Real, int D>
 __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
-                                             const AdjBufs<Real>& A, const AdjParams& AP, int n) {
+                                             const AdjBufs<Real>& A, const AdjParams& AP, int n, double* lthout) {
   constexpr int Q = Lat<D>::Q;
-  using CT = double;
+  using CT = Real;
+  using TT = Tan4<Real>;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
@@ -595,27 +663,29 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   });
   const CT cm = ::sqrt(dotv<CT, D>(C, C));
   CT lci[3] = {lco[0], lco[1], lco[2]};
-  double lth = 0.0;
+  CT lth = CT(0);
   if (cm > (CT)P.eps_c) {
     CT ch[3] = {C[0] / cm, C[1] / cm, D == 3 ? C[2] / cm : CT(0)};
     CT lch[3], lcm = CT(0);
     if ((fl & FL_WET) && P.scheme != 0) {
-      Tan4 nn[3], w3[3];
+      TT nn[3], w3[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        nn[a] = Tan4(ch[a]);
-        if (a < D) nn[a].d[a] = 1.0;
-        w3[a] = Tan4(a < D ? (double)G.nw[a * P.Np + n] : 0.0);
+        nn[a].v = ch[a];
+        if (a < D) nn[a].d[a] = CT(1);
+        w3[a].v = a < D ? G.nw[a * P.Np + n] : Real(0);
       }
-      constexpr double deg = 3.14159265358979323846 / 180.0;
-      const double ctv = (double)G.cos_t[n], stv = (double)G.sin_t[n];
-      Tan4 ct(ctv), st(stv);
+      constexpr CT deg = (CT)(3.14159265358979323846 / 180.0);
+      const CT ctv = G.cos_t[n], stv = G.sin_t[n];
+      TT ct, st;
+      ct.v = ctv;
+      st.v = stv;
       ct.d[3] = -stv * deg;
       st.d[3] = ctv * deg;
       if (P.scheme == 1)
-        scheme1<Tan4, D>(nn, w3, ct, Tan4((fl & FL_S1POS) ? 1.0 : -1.0), Tan4(P.eps_f), Tan4(P.eps_v));
+        scheme1<TT, D>(nn, w3, ct, TT((fl & FL_S1POS) ? 1.0 : -1.0), TT(P.eps_f), TT(P.eps_v));
       else
-        scheme2<Tan4, D>(nn, w3, ct, st, Tan4(P.eps_v));
+        scheme2<TT, D>(nn, w3, ct, st, TT(P.eps_v));
       // C_out = |C| n_wet
       CT lnt[3];
 #pragma unroll
@@ -652,18 +722,16 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   o.z = D == 3 ? (Real)lci[2] : Real(0);
   o.w = Real(0);
   A.lc[v] = o;
-  if (lth != 0.0) {
-    double4 g = A.gacc[n];
-    g.w += lth;
-    A.gacc[n] = g;
-    A.lth[v] += lth * idf;
-  }
+  if (lth != CT(0)) A.lth[v] += (double)lth * idf;
+  *lthout = (double)lth;
 }
 
 template <class Real, int D>
 __global__ void __launch_bounds__(256) ka_normal(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A, AdjParams AP) {
   const int n = node_id();
-  if (n < P.N) d_adj_normal<Real, D>(P, G, R, A, AP, n);
+  double lth = 0.0;
+  if (n < P.N) d_adj_normal<Real, D>(P, G, R, A, AP, n, &lth);
+  block_accumulate<256, 1>(&lth, 3, A.pacc);
 }
 
 // ------------------------------------------------------- ka_sb_phi, ka_phi
@@ -844,21 +912,6 @@ __global__ void ka_idf(StepParams P, Geo<Real> G, double* idf) {
     if (G.nbr[(i - 1) * P.Np + n] == kBounce) den += Lat<D>::w(i);
   });
   idf[n] = den > 0.0 ? 1.0 / den : 0.0;
-}
-
-// Per-block partial sums of the accumulated parameter adjoints.
-template <class Real, int BS>
-__global__ void __launch_bounds__(BS) ka_grad_part(int N, const double4* gacc, double* part) {
-  const int n = node_id();
-  double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (n < N) g = gacc[n];
-  __shared__ double sh[BS / 64];
-  const double q[4] = {g.x, g.y, g.z, g.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double t = block_sum<BS>(q[k], sh);
-    if (threadIdx.x == 0) part[blockIdx.x * 4 + k] = t;
-  }
 }
 
 // dJ/dtheta(s) at each solid boundary point: the transpose of the weighted

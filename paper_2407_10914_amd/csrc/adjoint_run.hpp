@@ -65,7 +65,12 @@ class AdjointRun {
   V4 *na_ = nullptr, *lcf_ = nullptr, *ln_ = nullptr, *lc_ = nullptr;
   Real *lk_ = nullptr, *lphi_ = nullptr, *iden_ = nullptr;
   double *idf_ = nullptr, *lth_ = nullptr, *part_ = nullptr, *sums_ = nullptr;
-  double4* gacc_ = nullptr;
+  double* pacc_ = nullptr;
+  // front fields (phase, normal, colour gradient, force) of the state at
+  // t0 + k for each ring index k, kept from the recomputation so the reverse
+  // step does not evaluate the front stages again; empty when the memory was
+  // not available (the reverse step then recomputes them)
+  std::vector<Grids<Real>> fg_;
   int p_ = 0;  // the current adjoint lives in lf_[p_], lr_
 
   void* get(size_t b) {
@@ -107,39 +112,55 @@ class AdjointRun {
     return e;
   }
   AdjBufs<Real> bufs() const {
-    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_, na_, lcf_, lk_, ln_, lc_, lphi_, iden_, idf_, gacc_, lth_};
+    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_, na_, lcf_, lk_, ln_, lc_, lphi_, iden_, idf_, pacc_, lth_};
   }
 
-  // one forward step from `in` into slot `out`
+  // one forward step from `in` into slot `out`; the front fields go to the
+  // ring index k's grids when they are kept (k < 0: the engine's grids)
   template <int D, class In>
-  void fstep(const In& in, const Slot& out) {
+  void fstep(const In& in, const Slot& out, int64_t k = -1) {
     auto o = out_of<D>(out);
+    const Grids<Real> saved = E.R_;
+    if (k >= 0 && !fg_.empty()) E.R_ = fg_[(size_t)k];
     E.template front_with<D>(in, 5);
     E.launch(-1, k_main<Real, D, BS, MODE_STEP, In, decltype(o)>, E.P_.N, E.P_, E.G_, E.R_, in, o, MacroOut{},
              ObsOut{});
+    E.R_ = saved;
   }
 
   // the reverse stages after the node stage (shared by the steps and the
   // flux terminal condition)
   template <int D>
-  void reverse_tail() {
+  void reverse_tail(const Grids<Real>& R) {
     const StepParams& P = E.P_;
     const AdjBufs<Real> A = bufs();
-    E.launch(-1, ka_curv<Real, D, false>, P.N, P, E.G_, E.R_, A);
-    if (P.nsb) E.launch(-1, ka_curv<Real, D, true>, P.nsb, P, E.G_, E.R_, A);
-    E.launch(-1, ka_normal<Real, D>, P.N, P, E.G_, E.R_, A, AP_);
+    E.launch(-1, ka_curv<Real, D, false>, P.N, P, E.G_, R, A);
+    if (P.nsb) E.launch(-1, ka_curv<Real, D, true>, P.nsb, P, E.G_, R, A);
+    E.launch(-1, ka_normal<Real, D>, P.N, P, E.G_, R, A, AP_);
     if (P.nsb) E.launch(-1, ka_sb_phi<Real, D>, P.nsb, P, E.G_, A);
     E.launch(-1, ka_phi<Real, D>, P.N, P, E.G_, A);
     p_ ^= 1;
   }
 
-  // lambda_{t} from lambda_{t+1}, the state at t being `in`
+  // lambda_{t} from lambda_{t+1}, the state at t being `in` (ring index k)
   template <int D, class In>
-  void rstep(const In& in) {
+  void rstep(const In& in, int64_t k) {
     const StepParams& P = E.P_;
-    E.template front_with<D>(in, 5);
-    E.launch(-1, ka_node<Real, D, false, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
-    reverse_tail<D>();
+    Grids<Real> R = E.R_;
+    if (!fg_.empty()) {
+      R = fg_[(size_t)k];
+    } else {
+      E.template front_with<D>(in, 5);
+    }
+    if constexpr (D == 3) {
+      if (P.collision == 1)
+        E.launch(-1, ka_node<Real, D, false, true, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+      else
+        E.launch(-1, ka_node<Real, D, false, false, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+    } else {
+      E.launch(-1, ka_node<Real, D, false, false, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+    }
+    reverse_tail<D>(R);
   }
 
   // objective of the state `in` (into sums_) and the terminal adjoint
@@ -151,8 +172,15 @@ class AdjointRun {
     E.launch(-1, ka_obj<Real, D, BS, In>, P.N, P, E.G_, E.R_, in, AP_, part_);
     hipLaunchKernelGGL(ka_reduce<Real>, dim3(kObjN), dim3(256), 0, E.stream_, (const double*)part_, nb, kObjN, sums_);
     if (AP_.objective == 2) {
-      E.launch(-1, ka_node<Real, D, true, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
-      reverse_tail<D>();
+      if constexpr (D == 3) {
+        if (P.collision == 1)
+          E.launch(-1, ka_node<Real, D, true, true, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
+        else
+          E.launch(-1, ka_node<Real, D, true, false, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
+      } else {
+        E.launch(-1, ka_node<Real, D, true, false, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
+      }
+      reverse_tail<D>(E.R_);
     } else {
       E.launch(-1, ka_seed_local<Real, D, In>, P.N, P, E.G_, in, AP_, (const double*)sums_, lf_[p_], lr_);
     }
@@ -172,6 +200,29 @@ class AdjointRun {
     for (auto& s : ck) ok = ok && new_slot(&s);
     for (auto& s : tmp) ok = ok && new_slot(&s);
     for (auto& s : ring) ok = ok && new_slot(&s);
+    // front fields per ring index (optional: skipped when memory is short)
+    {
+      std::vector<Grids<Real>> g((size_t)K);
+      bool gok = true;
+      const size_t m0 = mem_.size(), b0 = bytes_;
+      for (auto& x : g) {
+        x.phi = (Real*)get(sizeof(Real) * V);
+        x.n = (V4*)get(sizeof(V4) * V);
+        x.c = (V4*)get(sizeof(V4) * Np);
+        x.f = (V4*)get(sizeof(V4) * Np);
+        gok = gok && x.phi && x.n && x.c && x.f;
+        if (!gok) break;
+      }
+      if (gok) {
+        fg_ = g;
+      } else {
+        while (mem_.size() > m0) {
+          E.al_->put(mem_.back());
+          mem_.pop_back();
+        }
+        bytes_ = b0;
+      }
+    }
     for (int k = 0; k < 2; ++k) lf_[k] = (Real*)get(sizeof(Real) * Q * Np);
     lr_ = (V2*)get(sizeof(V2) * Np);
     na_ = (V4*)get(sizeof(V4) * Np);
@@ -183,12 +234,12 @@ class AdjointRun {
     iden_ = (Real*)get(sizeof(Real) * V);
     idf_ = (double*)get(sizeof(double) * Np);
     lth_ = (double*)get(sizeof(double) * V);
-    gacc_ = (double4*)get(sizeof(double4) * Np);
     const int nb = (P.N + BS - 1) / BS;
+    pacc_ = (double*)get(sizeof(double) * 4 * (size_t)nb);
     part_ = (double*)get(sizeof(double) * 4 * (size_t)(nb + 1));
     sums_ = (double*)get(sizeof(double) * 8);
     ok = ok && lf_[0] && lf_[1] && lr_ && na_ && lcf_ && lk_ && ln_ && lc_ && lphi_ && iden_ && idf_ && lth_ &&
-         gacc_ && part_ && sums_;
+         pacc_ && part_ && sums_;
     if (!ok) {
       E.err_ = "device allocation for the adjoint failed";
       return CG_ENOMEM;
@@ -204,9 +255,14 @@ class AdjointRun {
     zero(lphi_, sizeof(Real) * V);
     zero(iden_, sizeof(Real) * V);
     zero(lth_, sizeof(double) * V);
-    zero(gacc_, sizeof(double4) * Np);
+    zero(pacc_, sizeof(double) * 4 * (size_t)nb);
     zero(lr_, sizeof(V2) * Np);
     zero(sums_, sizeof(double) * 8);
+    // grid voxels that no stage writes (interior solid) are read as zeros
+    for (auto& x : fg_) {
+      zero(x.phi, sizeof(Real) * V);
+      zero(x.n, sizeof(V4) * V);
+    }
     if (e != hipSuccess) {
       E.err_ = hipGetErrorString(e);
       return CG_EHIP;
@@ -260,12 +316,13 @@ class AdjointRun {
         out = ck[(size_t)(t1 / K - 1)];
       else
         out = tmp[(size_t)(t1 & 1)];
+      const int64_t kg = t >= t_last ? t - t_last : -1;
       if (t == 0) {
-        with_ck(0, [&](const auto& in) { fstep<D>(in, out); });
+        with_ck(0, [&](const auto& in) { fstep<D>(in, out, kg); });
       } else if (t > t_last) {
-        fstep<D>(in_of<D>(ring[(size_t)(t - t_last - 1)]), out);
+        fstep<D>(in_of<D>(ring[(size_t)(t - t_last - 1)]), out, kg);
       } else if (t % K == 0) {
-        fstep<D>(in_of<D>(ck[(size_t)(t / K - 1)]), out);
+        fstep<D>(in_of<D>(ck[(size_t)(t / K - 1)]), out, kg);
       } else {
         fstep<D>(in_of<D>(tmp[(size_t)(t & 1)]), out);
       }
@@ -279,15 +336,14 @@ class AdjointRun {
       const int64_t L = c == nseg - 1 ? Llast : K;
       if (c != nseg - 1) {
         for (int64_t k = 0; k < L; ++k)
-          with_seg(c, k, [&](const auto& in) { fstep<D>(in, ring[(size_t)k]); });
+          with_seg(c, k, [&](const auto& in) { fstep<D>(in, ring[(size_t)k], k); });
       }
-      for (int64_t k = L - 1; k >= 0; --k) with_seg(c, k, [&](const auto& in) { rstep<D>(in); });
+      for (int64_t k = L - 1; k >= 0; --k) with_seg(c, k, [&](const auto& in) { rstep<D>(in, k); });
     }
     (void)hipEventRecord(e2, st);
 
     // parameter gradients
-    E.launch(-1, ka_grad_part<Real, BS>, P.N, P.N, (const double4*)gacc_, part_);
-    hipLaunchKernelGGL(ka_reduce<Real>, dim3(4), dim3(256), 0, st, (const double*)part_, nb, 4, sums_ + 4);
+    hipLaunchKernelGGL(ka_reduce<Real>, dim3(4), dim3(256), 0, st, (const double*)pacc_, nb, 4, sums_ + 4);
     if (g->dJ_dtheta_field) {
       const size_t nbv = (V + 255) / 256;
       hipLaunchKernelGGL((ka_fill<Real, double>), dim3((unsigned)nbv), dim3(256), 0, st, V, g->dJ_dtheta_field, 0.0);

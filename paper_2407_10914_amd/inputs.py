@@ -132,7 +132,7 @@ def _gaussian_field(n: int, corr: float, seed: int) -> np.ndarray:
     s = corr / np.sqrt(2.0)
     kz, ky, kx = np.meshgrid(k, k, kr, indexing="ij")
     filt = np.exp(-0.5 * s * s * (kx * kx + ky * ky + kz * kz))
-    field = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(n, n, n))
+    field = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(n, n, n), axes=(0, 1, 2))
     return field
 
 
@@ -213,6 +213,21 @@ def _grf_rock_solid(n, nz, corr, porosity, seed, buffer, tol):
         raw = 0.5 * (lo + hi)
         fluid, por = build(raw)
     return (~fluid).astype(np.uint8)
+
+
+def drainage_rock(n=128, corr=8.0, porosity=0.22, seed=MASTER_SEED, buffer=10, theta=40.0, nz=None):
+    """Body-force drainage through the synthetic rock (the adjoint workload):
+    the rock of grf_rock with the z axis periodic (the two ten-layer buffers
+    meet), non-wetting red in the inlet buffer z < buffer and wetting blue
+    elsewhere, and a per-voxel contact-angle field that is `theta` degrees on
+    every solid voxel.  Returns (case, theta_field)."""
+    c = grf_rock(n=n, corr=corr, porosity=porosity, seed=seed, buffer=buffer, nz=nz)
+    nzz = c.solid.shape[0]
+    zz = np.arange(nzz)[:, None, None] * np.ones(c.solid.shape)
+    phi = np.where(zz < buffer, 1.0, -1.0)
+    theta_field = np.where(c.solid == 1, float(theta), 0.0)
+    meta = dict(c.meta, kind="drainage_rock", theta=float(theta))
+    return Case(c.solid, phi, (0, 0, 1), 3, meta), theta_field
 
 
 @functools.lru_cache(maxsize=None)
