@@ -51,9 +51,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_fluid):
+def read_traffic(n_fluid, block):
     """HBM bytes per k_main launch from the committed rocprofv3 PMC summary,
-    or None when missing or taken from other kernel sources."""
+    or None when missing, taken from other kernel sources or at another
+    block size."""
     path = os.path.join(ROOT, "profiles", "k_main_rock256_f32_pmc.md")
     if not os.path.exists(path):
         return None
@@ -63,6 +64,8 @@ def read_traffic(n_fluid):
             body = line.strip()[4:-3].split("traffic:", 1)[1]
             meta = json.loads(body)
     if not meta or meta.get("kernel_hash") != kernel_source_hash() or meta.get("n_fluid") != n_fluid:
+        return None
+    if meta.get("block", 256) != block:
         return None
     return meta.get("bytes_per_launch")
 
@@ -131,6 +134,7 @@ def batched_leg(steps, warmup, count=64, ref_edge=256):
     torch.cuda.empty_cache()
     # the single large run of the same setup
     big = make(ref_edge, 90.0, 1)
+    big.tune(reps=3)
     big.step(warmup)
     big.sync()
     torch.cuda.synchronize()
@@ -167,6 +171,8 @@ def adjoint_leg(n_steps=2000, K=100, n=128):
               theta_deg=40.0, collision=1, g=(0.0, 0.0, 1e-5))
     sim = Sim(case.solid, precision="f32", theta_field=th, **kw)
     n_fluid = sim.info()["fluid"]
+    sim.set_phase(case.phi0)
+    sim.tune(reps=3)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     sim.set_phase(case.phi0)
@@ -210,6 +216,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep 256 threads per block for every kernel")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-k", type=int, default=100)
     ap.add_argument("--copy-calib", action="store_true",
@@ -233,6 +240,11 @@ def main():
     n_fluid = info["fluid"]
     print(f"# setup {time.perf_counter() - t_setup:.1f} s, fluid nodes {n_fluid}, voxels {info['voxels']}",
           file=sys.stderr, flush=True)
+    tuning = None
+    if not args.no_tune:
+        tuning = sim.tune(reps=5)
+        print(f"# tuned: {tuning}", file=sys.stderr, flush=True)
+    main_block = int(tuning.split("k_main: block ")[1].split()[0]) if tuning else 256
 
     sim.step(args.warmup)
     sim.sync()
@@ -260,10 +272,11 @@ def main():
     vox_mlups = info["voxels"] * args.steps / (gpu_ms / 1e3) / 1e6
     main_avg_s = main_ms / max(main_n, 1) / 1e3
     achieved = B_ALG_F32_D3Q19 * n_fluid / main_avg_s / 1e9
-    traffic = read_traffic(n_fluid)
+    traffic = read_traffic(n_fluid, main_block)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_main",
-            "bytes_alg_per_launch": B_ALG_F32_D3Q19 * n_fluid, "avg_launch_us": round(main_avg_s * 1e6, 2)}
+            "bytes_alg_per_launch": B_ALG_F32_D3Q19 * n_fluid, "avg_launch_us": round(main_avg_s * 1e6, 2),
+            "block": main_block}
     step_frac = mlups * 1e6 * B_ALG_F32_D3Q19 / (HBM_PEAK_GBS * 1e9)
     del sim
     torch.cuda.empty_cache()
@@ -302,7 +315,7 @@ def main():
                                "porosity 0.22, Zou-He drho=0.02, Scheme-I 30 deg, MRT, FP32",
                    "fluid_nodes": n_fluid, "voxels": info["voxels"], "voxel_mlups": round(vox_mlups, 1),
                    "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3),
-                   "sat_nw_mass": obs["sat_nw_mass"], "batched": batched, "adjoint": adj},
+                   "sat_nw_mass": obs["sat_nw_mass"], "tuning": tuning, "batched": batched, "adjoint": adj},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

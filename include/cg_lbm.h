@@ -228,6 +228,13 @@ cg_status cg_lbm_set_timing(cg_lbm* h, int mask);
 cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n);
 cg_status cg_lbm_reset_timing(cg_lbm* h);
 
+/* Block-size autotuner of one run: times reps steps with every kernel at 64,
+ * then 128, then 256 threads per block (HIP events around each launch) and
+ * keeps the fastest size per kernel for the run's later steps.  Advances the
+ * run by 3 * reps steps (tune before taking the steps that matter).  report
+ * (may be NULL) receives the choice and the times. */
+cg_status cg_lbm_tune(cg_lbm* h, int reps, char* report, size_t report_len);
+
 /* ---------------------------------------------------------------------- */
 /* Parameters that can change between calls. */
 

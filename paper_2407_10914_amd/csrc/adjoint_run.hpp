@@ -123,8 +123,7 @@ class AdjointRun {
     const Grids<Real> saved = E.R_;
     if (k >= 0 && !fg_.empty()) E.R_ = fg_[(size_t)k];
     E.template front_with<D>(in, 5);
-    E.launch(-1, k_main<Real, D, BS, MODE_STEP, In, decltype(o)>, E.P_.N, E.P_, E.G_, E.R_, in, o, MacroOut{},
-             ObsOut{});
+    E.template launch_main<D>(in, o);
     E.R_ = saved;
   }
 

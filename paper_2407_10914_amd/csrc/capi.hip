@@ -357,6 +357,18 @@ cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, dou
   return CG_OK;
 }
 
+cg_status cg_lbm_tune(cg_lbm* h, int reps, char* report, size_t report_len) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  std::string rep;
+  int rc = h->eng->tune(reps, &rep);
+  if (rc != CG_OK) return engine_status(h, rc);
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return CG_OK;
+}
+
 cg_status cg_lbm_reset_timing(cg_lbm* h) {
   if (!h) return fail(CG_EINVAL, "NULL handle");
   h->eng->reset_timing();

@@ -8,6 +8,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,13 @@ class Engine final : public EngineBase {
 
   int init(const HostSetup& S, const StepParams& P, int block, Alloc* al, hipStream_t st,
            std::string* err) override {
-    (void)block;
+    if (block != 0) {
+      if (block != 64 && block != 128 && block != 256) {
+        *err = "block must be 64, 128 or 256";
+        return CG_EINVAL;
+      }
+      for (int k = 0; k < K_COUNT; ++k) bs_[k] = block;
+    }
     al_ = al;
     stream_ = st;
     P_ = P;
@@ -315,6 +322,60 @@ class Engine final : public EngineBase {
     return CG_OK;
   }
 
+  // Block size per kernel: time `reps` steps at each of 64, 128 and 256
+  // threads (HIP events around every launch) and keep the fastest per
+  // kernel.  Advances the run by 3 * reps steps.
+  int tune(int reps, std::string* report) override {
+    if (reps < 1) reps = 1;
+    const int sizes[3] = {64, 128, 256};
+    double best[K_COUNT];
+    int pick[K_COUNT];
+    for (int k = 0; k < K_COUNT; ++k) {
+      best[k] = 1e300;
+      pick[k] = bs_[k];
+    }
+    const int saved_mask = timing_;
+    CG_HIP(hipStreamSynchronize(stream_));
+    collect();
+    int64_t c0[K_COUNT];
+    double m0[K_COUNT];
+    for (int k = 0; k < K_COUNT; ++k) {
+      c0[k] = tcount_[k];
+      m0[k] = tms_[k];
+    }
+    std::ostringstream os;
+    for (int b : sizes) {
+      for (int k = 0; k < K_COUNT; ++k) bs_[k] = b;
+      timing_ = -1;
+      int rc = step(reps);
+      if (rc != CG_OK) return rc;
+      CG_HIP(hipStreamSynchronize(stream_));
+      collect();
+      for (int k = 0; k < K_COUNT; ++k) {
+        const int64_t n = tcount_[k] - c0[k];
+        if (n > 0) {
+          const double avg = (tms_[k] - m0[k]) / (double)n;
+          if (avg < best[k]) {
+            best[k] = avg;
+            pick[k] = b;
+          }
+        }
+        c0[k] = tcount_[k];
+        m0[k] = tms_[k];
+      }
+    }
+    timing_ = saved_mask;
+    for (int k = 0; k < K_COUNT; ++k) {
+      bs_[k] = pick[k];
+      if (best[k] < 1e300) os << kKernelNames[k] << ": block " << pick[k] << " " << best[k] * 1e3 << " us; ";
+    }
+    if (report) *report = os.str();
+    return CG_OK;
+  }
+  void blocks(int* out) const override {
+    for (int k = 0; k < K_COUNT; ++k) out[k] = bs_[k];
+  }
+
   void set_timing(int mask) override { timing_ = mask; }
   int kernel_times(int64_t* counts, double* ms) override {
     CG_HIP(hipStreamSynchronize(stream_));
@@ -373,6 +434,7 @@ class Engine final : public EngineBase {
   Alloc* al_ = nullptr;
   hipStream_t stream_ = nullptr;
   int dim_ = 3, Q_ = 19, nsb_ = 0, cur_ = 0;
+  int bs_[K_COUNT] = {256, 256, 256, 256, 256, 256};
   bool pre_ = true;
   Real* fr_[2] = {nullptr, nullptr};
   Real* fb_[2] = {nullptr, nullptr};
@@ -431,8 +493,12 @@ class Engine final : public EngineBase {
 
   template <class K, class... Args>
   void launch(int kid, K kern, int nthreads, Args... args) {
+    launch_bs(kid, kid >= 0 ? bs_[kid] : BS, kern, nthreads, args...);
+  }
+  template <class K, class... Args>
+  void launch_bs(int kid, int bs, K kern, int nthreads, Args... args) {
     if (nthreads <= 0) return;
-    const int nb = (nthreads + BS - 1) / BS;
+    const int nb = (nthreads + bs - 1) / bs;
     hipEvent_t a = nullptr, b = nullptr;
     const bool tm = kid >= 0 && (timing_ & (1 << kid));
     if (tm) {
@@ -440,7 +506,7 @@ class Engine final : public EngineBase {
       b = get_event();
       (void)hipEventRecord(a, stream_);
     }
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(BS), 0, stream_, args...);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), 0, stream_, args...);
     if (tm) {
       (void)hipEventRecord(b, stream_);
       recs_.push_back({kid, a, b});
@@ -493,12 +559,29 @@ class Engine final : public EngineBase {
       front_with<D>(in_post<D>(), upto);
   }
 
+  // the step kernel at the tuned block size (its launch bounds follow it)
+  template <int D, class In, class Out>
+  void launch_main(const In& in, const Out& out) {
+    switch (bs_[K_MAIN]) {
+      case 64:
+        launch_bs(K_MAIN, 64, k_main<Real, D, 64, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, MacroOut{},
+                  ObsOut{});
+        break;
+      case 128:
+        launch_bs(K_MAIN, 128, k_main<Real, D, 128, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, MacroOut{},
+                  ObsOut{});
+        break;
+      default:
+        launch_bs(K_MAIN, 256, k_main<Real, D, 256, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, MacroOut{},
+                  ObsOut{});
+    }
+  }
+
   template <int D, class In>
   void step_with(const In& in) {
     auto out = out_next<D>();
     front_with<D>(in, 5);
-    launch(K_MAIN, k_main<Real, D, BS, MODE_STEP, In, decltype(out)>, P_.N, P_, G_, R_, in, out, MacroOut{},
-           ObsOut{});
+    launch_main<D>(in, out);
   }
   template <int D>
   void one_step() {

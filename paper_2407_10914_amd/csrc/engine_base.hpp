@@ -59,6 +59,8 @@ struct EngineBase {
   virtual int adjoint(const cg_adjoint_spec& sp, cg_gradients* g) = 0;
   virtual int set_angles(const double* cos_t, const double* sin_t, const unsigned* flags) = 0;
   virtual int set_body_force(const double* g) = 0;
+  virtual int tune(int reps, std::string* report) = 0;
+  virtual void blocks(int* out) const = 0;
   virtual void set_timing(int mask) = 0;
   virtual int kernel_times(int64_t* counts, double* ms) = 0;
   virtual void reset_timing() = 0;

@@ -203,6 +203,16 @@ struct InCanon {
     r = (CT)fr[i * Np + s];
     x = (CT)fb[i * Np + s];
   }
+  // pulled direction i >= 1 of node n with pull-table entry s (see load_node)
+  template <int i, class CT>
+  __device__ __forceinline__ void get_pull(int s, int n, CT& r, CT& x) const {
+    constexpr int o = opp<D>(i);
+    const int idx = s >= 0 ? i * Np + s : o * Np + n;
+    const CT a = (CT)fr[idx], b = (CT)fb[idx];
+    const bool open = s < kBounce;
+    r = open ? CT(0) : a;
+    x = open ? CT(0) : b;
+  }
 };
 
 // Compact post-collision state (float path); x = g = f^t - w rho0.
@@ -233,6 +243,32 @@ struct InCompact {
     }
     r = r0;
     x = t;
+  }
+  // pulled direction i >= 1 of node n with pull-table entry s (see load_node):
+  // the same value as get<i>(s) from a fluid source, get<opp(i)>(n) for a
+  // bounce-back link (the rebuilt red term changes sign with e), 0 for an open
+  // face, without a branch
+  template <int i, class CT>
+  __device__ __forceinline__ void get_pull(int s, int n, CT& r, CT& x) const {
+    constexpr double w = Lat<D>::w(i);
+    constexpr int o = opp<D>(i);
+    const bool fl = s >= 0;
+    const int node = fl ? s : n;
+    const int idx = fl ? i * Np + s : o * Np + n;
+    const CT t = (CT)T[idx];
+    const float4 ac = AC[node];
+    const CT cc[3] = {(CT)ac.y, (CT)ac.z, (CT)ac.w};
+    CT ce = CT(0);
+    unroll<D>([&](auto A_) {
+      constexpr int d = A_;
+      constexpr int e = Lat<D>::e(i, d);
+      if constexpr (e == 1) ce = ce + cc[d];
+      if constexpr (e == -1) ce = ce - cc[d];
+    });
+    const CT r0 = (CT)ac.x * ((CT)w * (CT)rho0 + t) + (CT)w * (fl ? ce : -ce);
+    const bool open = s < kBounce;
+    r = open ? CT(0) : r0;
+    x = open ? CT(0) : t;
   }
 };
 
@@ -268,32 +304,27 @@ struct OutCompact {
 // Gather the pre-collision populations of node n (pull streaming with halfway
 // bounce-back: f_i(x) = f'_i(x - e_i) from a fluid source, f'_opp(i)(x) when
 // the source is solid; open-face unknowns are left 0 for the Zou-He step).
+// The pulled loads carry no branch, so all of them are issued back to back.
 template <int D, class In, class CT>
 __device__ __forceinline__ void load_node(const In& in, const int* nbr, int Np, int n, CT* fr, CT* fx) {
   constexpr int Q = Lat<D>::Q;
-  int src[Q];
   if constexpr (In::kPull) {
+    int src[Q];
     unroll<Q - 1>([&](auto I) {
       constexpr int i = I + 1;
       src[i] = nbr[(i - 1) * Np + n];
     });
-  }
-  unroll<Q>([&](auto I) {
-    constexpr int i = I;
-    if constexpr (In::kPull && i > 0) {
-      const int s = src[i];
-      if (s >= 0) {
-        in.template get<i>(s, fr[i], fx[i]);
-      } else if (s == kBounce) {
-        in.template get<opp<D>(i)>(n, fr[i], fx[i]);
-      } else {
-        fr[i] = CT(0);
-        fx[i] = CT(0);
-      }
-    } else {
+    in.template get<0>(n, fr[0], fx[0]);
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      in.template get_pull<i>(src[i], n, fr[i], fx[i]);
+    });
+  } else {
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
       in.template get<i>(n, fr[i], fx[i]);
-    }
-  });
+    });
+  }
 }
 
 // -------------------------------------------------------------- Zou-He faces
@@ -329,34 +360,54 @@ __device__ __forceinline__ void zh_out_color(CT* f, CT jc) {
 // inlet and chi-weighted outlet exactly as written.  Deviation layout
 // (x = f^t - w rho0): the red colour as written, the total with the deviation
 // densities (the weights of the known directions sum to 1 for both faces).
+// Both faces are evaluated on copies and merged by value selects: the inlet
+// sets directions {5, 11, 12, 15, 16}, the outlet {6, 13, 14, 17, 18}, and a
+// node is never both.  (Conditional stores into the node arrays would be
+// merged by the compiler into stores through a selected pointer, which moves
+// the arrays out of registers.)
 template <bool kDev, class CT>
 __device__ __forceinline__ void zou_he(const StepParams& P, unsigned fl, CT phi_up, CT* fr, CT* fx) {
-  if (fl & FL_IN) {
-    zh_in(fr, (CT)P.rin_r);
-    if constexpr (kDev)
-      zh_in(fx, (CT)(P.rho_in - P.rho0));
-    else
-      zh_in(fx, (CT)P.rin_b);
-  } else if (fl & FL_OUT) {
-    CT jt;
-    if constexpr (kDev) {
-      CT S = fx[0] + fx[1] + fx[2] + fx[3] + fx[4] + fx[7] + fx[8] + fx[9] + fx[10];
-      CT T = fx[5] + fx[11] + fx[12] + fx[15] + fx[16];
-      jt = -(CT)(P.rho_out - P.rho0) + (S + CT(2) * T);
-      zh_out_color(fr, jt * (CT(0.5) * (CT(1) + phi_up)));
-      zh_out_color(fx, jt);
-    } else {
-      CT ft[19];
+  const bool in = fl & FL_IN;
+  const bool out = fl & FL_OUT;
+  CT ir[19], ix[19], orr[19], ox[19];
 #pragma unroll
-      for (int i = 0; i < 19; ++i) ft[i] = fr[i] + fx[i];
-      CT S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
-      CT T = ft[5] + ft[11] + ft[12] + ft[15] + ft[16];
-      jt = -(CT)P.rho_out + (S + CT(2) * T);
-      CT chr = CT(0.5) * (CT(1) + phi_up);
-      CT chb = CT(0.5) * (CT(1) - phi_up);
-      zh_out_color(fr, jt * chr);
-      zh_out_color(fx, jt * chb);
-    }
+  for (int i = 0; i < 19; ++i) {
+    ir[i] = fr[i];
+    ix[i] = fx[i];
+    orr[i] = fr[i];
+    ox[i] = fx[i];
+  }
+  zh_in(ir, (CT)P.rin_r);
+  if constexpr (kDev)
+    zh_in(ix, (CT)(P.rho_in - P.rho0));
+  else
+    zh_in(ix, (CT)P.rin_b);
+  if constexpr (kDev) {
+    CT S = ox[0] + ox[1] + ox[2] + ox[3] + ox[4] + ox[7] + ox[8] + ox[9] + ox[10];
+    CT T = ox[5] + ox[11] + ox[12] + ox[15] + ox[16];
+    const CT jt = -(CT)(P.rho_out - P.rho0) + (S + CT(2) * T);
+    zh_out_color(orr, jt * (CT(0.5) * (CT(1) + phi_up)));
+    zh_out_color(ox, jt);
+  } else {
+    CT ft[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) ft[i] = orr[i] + ox[i];
+    CT S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
+    CT T = ft[5] + ft[11] + ft[12] + ft[15] + ft[16];
+    const CT jt = -(CT)P.rho_out + (S + CT(2) * T);
+    const CT chr = CT(0.5) * (CT(1) + phi_up);
+    const CT chb = CT(0.5) * (CT(1) - phi_up);
+    zh_out_color(orr, jt * chr);
+    zh_out_color(ox, jt * chb);
+  }
+  constexpr int kIn[5] = {5, 11, 12, 15, 16};
+  constexpr int kOut[5] = {6, 13, 14, 17, 18};
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    fr[kIn[q]] = in ? ir[kIn[q]] : fr[kIn[q]];
+    fx[kIn[q]] = in ? ix[kIn[q]] : fx[kIn[q]];
+    fr[kOut[q]] = out ? orr[kOut[q]] : fr[kOut[q]];
+    fx[kOut[q]] = out ? ox[kOut[q]] : fx[kOut[q]];
   }
 }
 

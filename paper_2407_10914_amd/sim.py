@@ -48,7 +48,7 @@ class Sim:
     def __init__(self, solid, *, dim, periodic, tau_r=1.0, tau_b=1.0, sigma=0.0, beta=0.7, scheme=0,
                  theta_deg=90.0, theta_field=None, s1_line=0, bc=0, rho_in=1.0, rho_out=1.0, zeta_r=0.0,
                  g=(0.0, 0.0, 0.0), precision="f32", collision=None, rho0=1.0, eps_c=None, eps_f=None,
-                 eps_v=None, device=0, torch_alloc=True):
+                 eps_v=None, device=0, torch_alloc=True, block=0):
         lib = L.load()
         solid = np.ascontiguousarray(solid, dtype=np.uint8)
         if solid.ndim == 2:
@@ -75,6 +75,7 @@ class Sim:
             if v is not None:
                 setattr(opt, k, v)
         opt.device = device
+        opt.block = int(block)
         self._alloc = None
         if torch_alloc:
             self._alloc = TorchAllocator(device)
@@ -228,6 +229,12 @@ class Sim:
 
     def reset_timing(self):
         L.check(L.load().cg_lbm_reset_timing(self._h))
+
+    def tune(self, reps=5):
+        """Pick the block size of every step kernel (advances the run by 3*reps steps)."""
+        buf = C.create_string_buffer(1024)
+        L.check(L.load().cg_lbm_tune(self._h, int(reps), buf, 1024))
+        return buf.value.decode()
 
     def kernel_times(self):
         names = (C.c_char * 32 * 16)()

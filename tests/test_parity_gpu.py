@@ -173,3 +173,29 @@ def test_fp64_mass_conservation_and_oracle_observables_periodic_drop():
     a, b = g.observe(), o.observe()
     for k in ("mass_r", "mass_b", "p_in", "p_out", "vol_r", "u_max"):
         assert abs(a[k] - b[k]) <= 1e-12 * max(1.0, abs(b[k])), (k, a[k], b[k])
+
+
+@pytest.mark.parametrize("block", [64, 128])
+def test_block_size_leaves_fp64_results_bitwise(block):
+    """Every node is computed by one thread from the previous state, so the
+    block size (fixed by option, or chosen by the tuner) cannot change a bit."""
+    from paper_2407_10914_amd.sim import Sim
+
+    case, kw = c2_tube(scheme=2, theta=135.0, drive="type2", nz=40, wet_len=12)
+    fluid = case.solid == 0
+    g = Sim(case.solid, precision="f64", **kw)
+    g.set_phase(case.phi0)
+    rep = g.tune(reps=2)
+    _say("tuned", rep)
+    o = _orc(case, kw)
+    o.step(6)
+    _compare_macro(g, o, fluid, 0.0, "tuned t=6")
+    g.step(10)
+    o.step(10)
+    _compare_macro(g, o, fluid, 0.0, "tuned t=16")
+    # a fixed block size from the options
+    h = Sim(case.solid, precision="f64", block=block, **kw)
+    h.set_phase(case.phi0)
+    h.step(16)
+    assert np.array_equal(h.field("rho_r"), g.field("rho_r"))
+    assert np.array_equal(h.field("u"), g.field("u"))
