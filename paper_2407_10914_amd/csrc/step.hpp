@@ -161,24 +161,24 @@ __device__ __forceinline__ Pos make_pos(const StepParams& P, int v, bool face) {
   return p;
 }
 
+// Branch-free: the wrapped/clamped index is formed for every node (from the
+// zero coordinates of an interior node it is simply unused) and selected.
+__device__ __forceinline__ int wrap_or_clamp(int x, int n, bool per) {
+  const int w = x + (x < 0 ? n : 0) - (x >= n ? n : 0);
+  const int c = min(max(x, 0), n - 1);
+  return per ? w : c;
+}
+
 template <int D, int i>
 __device__ __forceinline__ int nb_vox(const StepParams& P, const Pos& p) {
   constexpr int ex = Lat<D>::e(i, 0), ey = Lat<D>::e(i, 1), ez = Lat<D>::e(i, 2);
-  if (!p.face) return p.v + ex + P.nx * (ey + P.ny * ez);
+  const int fast = p.v + ex + P.nx * (ey + P.ny * ez);
   int x = p.x + ex, y = p.y + ey, z = p.z + ez;
-  if constexpr (ex != 0) {
-    if (x < 0) x = P.per[0] ? x + P.nx : 0;
-    if (x >= P.nx) x = P.per[0] ? x - P.nx : P.nx - 1;
-  }
-  if constexpr (ey != 0) {
-    if (y < 0) y = P.per[1] ? y + P.ny : 0;
-    if (y >= P.ny) y = P.per[1] ? y - P.ny : P.ny - 1;
-  }
-  if constexpr (ez != 0) {
-    if (z < 0) z = P.per[2] ? z + P.nz : 0;
-    if (z >= P.nz) z = P.per[2] ? z - P.nz : P.nz - 1;
-  }
-  return x + P.nx * (y + P.ny * z);
+  if constexpr (ex != 0) x = wrap_or_clamp(x, P.nx, P.per[0] != 0);
+  if constexpr (ey != 0) y = wrap_or_clamp(y, P.ny, P.per[1] != 0);
+  if constexpr (ez != 0) z = wrap_or_clamp(z, P.nz, P.per[2] != 0);
+  const int slow = x + P.nx * (y + P.ny * z);
+  return p.face ? slow : fast;
 }
 
 template <class Real, int D>
