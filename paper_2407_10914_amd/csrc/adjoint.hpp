@@ -635,17 +635,18 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   const Vec4<Real> l4 = A.ln[v];
   CT ln[3] = {(CT)l4.x, (CT)l4.y, (CT)l4.z};
   if (idf != 0.0) {
+    // every neighbour is read (no branch per link, so the loads overlap); a
+    // voxel that is not a solid boundary point has iden = 0 and a finite
+    // lambda n, and adds an exact zero
     unroll<Q - 1>([&](auto J) {
       constexpr int j = J + 1;
       const int x = nb_vox<D, j>(P, ps);
       const Real id = A.iden[x];
-      if (id != Real(0)) {
-        const Vec4<Real> q = A.ln[x];
-        const CT c = (CT)Lat<D>::w(j) * (CT)id;
-        ln[0] = ln[0] + c * (CT)q.x;
-        ln[1] = ln[1] + c * (CT)q.y;
-        if constexpr (D == 3) ln[2] = ln[2] + c * (CT)q.z;
-      }
+      const Vec4<Real> q = A.ln[x];
+      const CT c = (CT)Lat<D>::w(j) * (CT)id;
+      ln[0] = ln[0] + c * (CT)q.x;
+      ln[1] = ln[1] + c * (CT)q.y;
+      if constexpr (D == 3) ln[2] = ln[2] + c * (CT)q.z;
     });
   }
   const Vec4<Real> f4 = A.lcf[n];
