@@ -218,12 +218,15 @@ int64_t cg_lbm_snapshot_bytes(const cg_lbm* h);
 cg_status cg_lbm_save(cg_lbm* h, void* dst);
 cg_status cg_lbm_load(cg_lbm* h, const void* src);
 
-/* Kernel timing: mask selects the kernels of cg_lbm_step whose every launch is
- * bracketed by HIP events on the handle's stream (bit k = k-th kernel in the
- * order cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n,
- * k_curv, k_main; -1 = all, 0 = off).  cg_lbm_kernel_times synchronises, then reports
- * for each kernel its name, launch count and total milliseconds since the
- * last reset (n: in = capacity, out = count). */
+/* Kernel timing: mask selects the kernels whose every launch is bracketed by
+ * HIP events on the handle's stream (bit k = k-th kernel in the order
+ * cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n, k_curv,
+ * k_main; -1 = all, 0 = off).  A time step runs k_phase, k_sb_phi, k_normal,
+ * k_sb_n and k_main (which evaluates the curvature and force of its node);
+ * k_curv stores them before the macroscopic fields and the observables.
+ * cg_lbm_kernel_times synchronises, then reports for each kernel its name,
+ * launch count and total milliseconds since the last reset (n: in =
+ * capacity, out = count). */
 cg_status cg_lbm_set_timing(cg_lbm* h, int mask);
 cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n);
 cg_status cg_lbm_reset_timing(cg_lbm* h);
@@ -327,8 +330,9 @@ cg_status cg_batch_set_graph(cg_batch* b, int on);
  * first when a run's state was just set.  report (may be NULL) receives a
  * summary. */
 cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len);
-/* total fluid nodes; chosen block and grid per stage (6 entries each, stages
- * in step order; grid 0 = one block per tile) */
+/* total fluid nodes; chosen block and grid per stage (5 entries each, stages
+ * in step order: phase, sb_phi, normal, sb_n, main; grid 0 = one block per
+ * tile) */
 cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid);
 
 #ifdef __cplusplus

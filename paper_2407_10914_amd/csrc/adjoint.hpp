@@ -156,6 +156,11 @@ __device__ __forceinline__ int coord_of(const StepParams& P, int v, int axis) {
   return axis == 0 ? x : (axis == 1 ? y : z);
 }
 
+template <int D, class Real>
+__device__ __forceinline__ void nbr_all(const Geo<Real>& G, int n, int* src) {
+  G.nbr.template all<Lat<D>::Q>(n, src);
+}
+
 // Populations of node n of the state `in` as canonical red and total values
 // (double for the FP64 state; the compact FP32 state keeps g = f^t - w rho0).
 template <class Real, int D, class In>
@@ -163,7 +168,7 @@ __device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G
                                          Real* fx, Real& rr, Real& rb, Real& rho) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
-  load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+  load_node<D>(in, G.nbr, n, fr, fx);
   Real a = fr[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) a = a + fr[i];
@@ -212,6 +217,9 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
   const CT rho0 = (CT)P.rho0;
+  // pull-table entries of the node (the reverse streaming uses them too)
+  int src[Q];
+  nbr_all<D>(G, n, src);
   // state at t: x_i = f^t_i (canonical) or g_i = f^t_i - w_i rho0 (compact).
   // The compact state needs only the totals here: rho^r follows from the
   // phase field k_phase computed from the same state, rho^r = rho (1 + phi)/2.
@@ -224,7 +232,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
         if constexpr (i == 0) {
           x[0] = (CT)in.T[n];
         } else {
-          const int s = G.nbr[(i - 1) * P.Np + n];
+          const int s = src[i];
           x[i] = (CT)(s >= 0 ? in.T[i * P.Np + s] : in.T[opp<D>(i) * P.Np + n]);
         }
       });
@@ -249,7 +257,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     rb = rho - rr;
   } else {
     Real fr[Q], fx[Q];
-    load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+    load_node<D>(in, G.nbr, n, fr, fx);
     CT a = fr[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) a = a + (CT)fr[i];
@@ -312,7 +320,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
         ri = n;
       } else {
         constexpr int o = opp<D>(i);
-        const int s = G.nbr[(o - 1) * P.Np + n];  // node at x - e_o = x + e_i
+        const int s = src[o];  // node at x - e_o = x + e_i
         li = s >= 0 ? i * P.Np + s : o * P.Np + n;
         ri = s >= 0 ? s : n;
       }
@@ -910,7 +918,7 @@ __global__ void ka_idf(StepParams P, Geo<Real> G, double* idf) {
   double den = 0.0;
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
-    if (G.nbr[(i - 1) * P.Np + n] == kBounce) den += Lat<D>::w(i);
+    if (G.nbr.template get<i>(n) == kBounce) den += Lat<D>::w(i);
   });
   idf[n] = den > 0.0 ? 1.0 / den : 0.0;
 }

@@ -43,8 +43,10 @@ struct RunDesc {
   PostOut<Real, D> out;
 };
 
-enum { ST_PHASE = 0, ST_SB_PHI, ST_NORMAL, ST_SB_N, ST_CURV, ST_MAIN, ST_COUNT };
-static const char* const kStageNames[ST_COUNT] = {"phase", "sb_phi", "normal", "sb_n", "curv", "main"};
+// Stages of one step (the main stage evaluates the curvature and force of its
+// node itself).
+enum { ST_PHASE = 0, ST_SB_PHI, ST_NORMAL, ST_SB_N, ST_MAIN, ST_COUNT };
+static const char* const kStageNames[ST_COUNT] = {"phase", "sb_phi", "normal", "sb_n", "main"};
 constexpr bool stage_on_sb(int st) { return st == ST_SB_PHI || st == ST_SB_N; }
 
 template <class Real, int D, int BS, int St>
@@ -65,8 +67,6 @@ __global__ void __launch_bounds__(BS) kb_stage(const RunDesc<Real, D>* __restric
       d_normal<Real, D>(d.P, d.G, d.R, n);
     } else if constexpr (St == ST_SB_N) {
       d_sb_n<Real, D>(d.P, d.G, d.R, n);
-    } else if constexpr (St == ST_CURV) {
-      d_curv<Real, D>(d.P, d.G, d.R, n);
     } else {
       if (n < d.P.N) d_main<Real, D, MODE_STEP>(d.P, d.G, d.R, d.in, d.out, MacroOut{}, n, nullptr);
     }
@@ -377,8 +377,6 @@ class Batch final : public BatchBase {
       case ST_SB_N:
         hipLaunchKernelGGL((kb_stage<Real, D, BS, ST_SB_N>), dim3(g), dim3(BS), 0, stream_, d, tl.first, ntiles, per);
         break;
-      case ST_CURV:
-        hipLaunchKernelGGL((kb_stage<Real, D, BS, ST_CURV>), dim3(g), dim3(BS), 0, stream_, d, tl.first, ntiles, per);
         break;
       default:
         hipLaunchKernelGGL((kb_stage<Real, D, BS, ST_MAIN>), dim3(g), dim3(BS), 0, stream_, d, tl.first, ntiles, per);
@@ -432,7 +430,7 @@ class Batch final : public BatchBase {
     int lg = 0;
     for (int64_t v = total_nodes_; v > 1; v >>= 1) ++lg;
     std::ostringstream os;
-    os << arch_ << "|D" << (dim_ == 3 ? "3Q19" : "2Q9") << "|" << (sizeof(Real) == 4 ? "f32" : "f64") << "|runs"
+    os << arch_ << "|stages" << ST_COUNT << "|D" << (dim_ == 3 ? "3Q19" : "2Q9") << "|" << (sizeof(Real) == 4 ? "f32" : "f64") << "|runs"
        << runs_.size() << "|n2^" << lg;
     return os.str();
   }

@@ -445,9 +445,9 @@ cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len) 
 cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid) {
   if (!b) return fail(CG_EINVAL, "NULL batch");
   if (total_nodes) *total_nodes = b->impl->total_nodes();
-  int bs[6], gr[6];
+  int bs[8], gr[8];
   b->impl->get_config(bs, gr);
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < 5; ++k) {
     if (block) block[k] = bs[k];
     if (grid) grid[k] = gr[k];
   }

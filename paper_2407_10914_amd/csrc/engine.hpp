@@ -61,12 +61,19 @@ class Engine final : public EngineBase {
     Q_ = S.Q;
     const size_t Np = (size_t)S.Np, V = (size_t)S.V;
     const size_t Q = (size_t)S.Q;
+    bool alloc_failed = false;
     auto dev = [&](size_t bytes) -> void* {
       void* p = al_->get(bytes);
-      if (p) owned_.push_back(p);
+      if (p)
+        owned_.push_back(p);
+      else
+        alloc_failed = true;
       return p;
     };
-    int* nbr = (int*)dev(sizeof(int) * (Q - 1) * Np);
+    const bool narrow = !S.nbr16.empty();
+    int* nbr = narrow ? nullptr : (int*)dev(sizeof(int) * (Q - 1) * Np);
+    int16_t* nbr16 = narrow ? (int16_t*)dev(sizeof(int16_t) * (Q - 1) * Np) : nullptr;
+    int* nbase = narrow ? (int*)dev(sizeof(int) * (Q - 1) * (size_t)S.ntiles) : nullptr;
     unsigned* vf = (unsigned*)dev(sizeof(unsigned) * Np);
     const size_t nsb = S.sb_vox.size();
     int* sbv = (int*)dev(sizeof(int) * (nsb ? nsb : 1));
@@ -96,11 +103,10 @@ class Engine final : public EngineBase {
       }
       state_bytes_ = sizeof(Real) * 2 * Q * Np;
     }
-    for (void* p : owned_)
-      if (!p) {
-        *err = "device allocation failed";
-        return CG_ENOMEM;
-      }
+    if (alloc_failed) {
+      *err = "device allocation failed";
+      return CG_ENOMEM;
+    }
     // upload
     std::vector<unsigned> vfp(Np, 0u);
     for (int n = 0; n < S.N; ++n) vfp[n] = (unsigned)S.node_vox[n] | (S.flags[n] << kVoxBits);
@@ -114,7 +120,12 @@ class Engine final : public EngineBase {
     auto up = [&](void* d, const void* h, size_t bytes) {
       if (e == hipSuccess && bytes) e = hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
     };
-    up(nbr, S.nbr.data(), sizeof(int) * (Q - 1) * Np);
+    if (narrow) {
+      up(nbr16, S.nbr16.data(), sizeof(int16_t) * (Q - 1) * Np);
+      up(nbase, S.nbr_base.data(), sizeof(int) * (Q - 1) * (size_t)S.ntiles);
+    } else {
+      up(nbr, S.nbr.data(), sizeof(int) * (Q - 1) * Np);
+    }
     up(vf, vfp.data(), sizeof(unsigned) * Np);
     up(sbv, S.sb_vox.data(), sizeof(int) * nsb);
     up(sbm, S.sb_mask.data(), sizeof(unsigned) * nsb);
@@ -129,7 +140,7 @@ class Engine final : public EngineBase {
       *err = std::string("upload failed: ") + hipGetErrorString(e);
       return CG_EHIP;
     }
-    G_ = Geo<Real>{nbr, vf, sbv, sbm, nw, ct, stt};
+    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles}, vf, sbv, sbm, nw, ct, stt};
     R_ = Grids<Real>{phi, ng, cv, fv};
     nsb_ = (int)nsb;
     dev_bytes_ = al_->total;
@@ -580,7 +591,7 @@ class Engine final : public EngineBase {
   template <int D, class In>
   void step_with(const In& in) {
     auto out = out_next<D>();
-    front_with<D>(in, 5);
+    front_with<D>(in, 4);
     launch_main<D>(in, out);
   }
   template <int D>

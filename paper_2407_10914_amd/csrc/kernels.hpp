@@ -1,9 +1,11 @@
 // __global__ kernels of the time step, observables and state transfer.
 // Instantiated per precision in kernels_f64.hip / kernels_f32.hip.
 //
-// Order within one step: k_phase -> k_sb_phi -> k_normal -> k_sb_n -> k_curv
-// -> k_main.  Each kernel needs the previous one complete over the whole
-// grid (stencils of radius 1 on the previous output).
+// Order within one step: k_phase -> k_sb_phi -> k_normal -> k_sb_n -> k_main
+// (k_main evaluates the curvature and force of its node itself; k_curv stores
+// them for the macroscopic fields, the observables and the adjoint).  Each
+// kernel needs the previous one complete over the whole grid (stencils of
+// radius 1 on the previous output).
 #pragma once
 
 #include "step.hpp"
@@ -29,9 +31,15 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
   if (fl & FL_IN) {
     phi = P.phi_in;
   } else {
-    const int src = (fl & FL_OUT) ? G.nbr[(kDirZp - 1) * P.Np + n] : n;
     Real fr[Q], fx[Q];
-    load_node<D>(in, G.nbr, P.Np, src, fr, fx);
+    if (fl & FL_OUT) {
+      // an outlet node takes the phase of the node upstream; its populations
+      // are pulled with that node's own (uniform) tile, by a whole-wave call
+      // made only by waves that hold an outlet node
+      load_outlet_upstream<D>(in, G.nbr, n, fr, fx);
+    } else {
+      load_node<D>(in, G.nbr, n, fr, fx);
+    }
     CT rr, rb, rho;
     if constexpr (kDev) {
       CT a = fr[0], t = (CT)Lat<D>::w(0) * P.rho0 + (CT)fx[0];
@@ -191,21 +199,20 @@ __global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
 
 // ------------------------------------------------------------------- k_curv
 // Curvature, Eq. (12), from the isotropic derivatives of n (same stencil as
-// Eq. 6), and the force F = 1/2 sigma kappa C (Eq. 5) + rho_o g (Eq. 36).
+// Eq. 6), and the force F = 1/2 sigma kappa C (Eq. 5) + rho_o g (Eq. 36), in
+// double arithmetic for either layout.  The time step evaluates this inside
+// k_main (the force of a node is used by that node only); k_curv stores it for
+// the macroscopic fields, the observables and the adjoint.
 template <class Real, int D>
-__device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int n) {
+__device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real>& R, int n, int v, const Pos& ps,
+                                           const Vec4<Real>& self, double* F, double& k) {
   constexpr int Q = Lat<D>::Q;
   using CT = double;
-  if (n >= P.N) return;
-  const unsigned vf = G.vf[n];
-  const int v = vox_of(vf);
-  const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
   Vec4<Real> nb[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     if constexpr (i > 0) nb[i] = R.n[nb_vox<D, i>(P, ps)];
   });
-  const Vec4<Real> self = R.n[v];
   CT d[3][3];
   unroll<D>([&](auto B_) {
     constexpr int b = B_;
@@ -228,7 +235,6 @@ __device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, 
     });
   });
   const CT nx_ = self.x, ny_ = self.y, nz_ = self.z;
-  CT k;
   if constexpr (D == 3) {
     k = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (nz_ * nz_ - CT(1)) * d[2][2] +
         (d[1][0] + d[0][1]) * nx_ * ny_ + (d[2][0] + d[0][2]) * nx_ * nz_ + (d[1][2] + d[2][1]) * nz_ * ny_;
@@ -237,9 +243,19 @@ __device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, 
   }
   const Vec4<Real> c = R.c[n];
   const CT C[3] = {(CT)c.x, (CT)c.y, (CT)c.z};
-  CT F[3] = {CT(0), CT(0), CT(0)};
+  F[0] = F[1] = F[2] = CT(0);
 #pragma unroll
   for (int a = 0; a < D; ++a) F[a] = P.half_sigma * k * C[a] + P.rg[a];
+}
+
+template <class Real, int D>
+__device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int n) {
+  if (n >= P.N) return;
+  const unsigned vf = G.vf[n];
+  const int v = vox_of(vf);
+  const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
+  double F[3], k;
+  curv_force<Real, D>(P, R, n, v, ps, R.n[v], F, k);
   Vec4<Real> o;
   o.x = (Real)F[0];
   o.y = (Real)F[1];
@@ -314,15 +330,26 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   Real fr[Q], fx[Q];
-  load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+  load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
     if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
   }
   Real rr, rb, rho, drho;
   node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
   const Real phi = R.phi[v];
-  const Vec4<Real> f4 = R.f[n];
   const Vec4<Real> n4 = R.n[v];
+  Vec4<Real> f4;
+  if constexpr (Mode == MODE_STEP) {
+    // curvature and force of this node (what k_curv stores)
+    double Fd[3], kd;
+    curv_force<Real, D>(P, R, n, v, make_pos(P, v, fl & FL_FACE), n4, Fd, kd);
+    f4.x = (Real)Fd[0];
+    f4.y = (Real)Fd[1];
+    f4.z = (Real)Fd[2];
+    f4.w = (Real)kd;
+  } else {
+    f4 = R.f[n];
+  }
   // velocity, Eq. (22), in the storage precision for the collision and in
   // double for the reported fields; the deviation layout balances momentum
   // with rho0 + sum g
@@ -517,7 +544,7 @@ __global__ void k_export(StepParams P, Geo<Real> G, Grids<Real> R, In in, double
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   double fr[Q], fx[Q];
-  load_node<D>(in, G.nbr, P.Np, n, fr, fx);
+  load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
     if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (double)R.phi[v], fr, fx);
   }

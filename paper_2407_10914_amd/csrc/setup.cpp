@@ -285,6 +285,47 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
   }
   S.fb_off.push_back((int)S.fb_vox.size());
   S.s1_line = wet.scheme1_line;
+
+  // 16-bit pull table: per (direction, tile of 256 nodes) the smallest offset
+  // s - n of a fluid source, per node the remainder
+  S.ntiles = Np >> kTileShift;
+  S.nbr16.assign((size_t)(Q - 1) * Np, (int16_t)kD16Bounce);
+  S.nbr_base.assign((size_t)(Q - 1) * S.ntiles, 0);
+  bool fits = true;
+  for (int i = 1; i < Q && fits; ++i) {
+    for (int t = 0; t < S.ntiles && fits; ++t) {
+      const int n0 = t << kTileShift, n1 = std::min(N, (t + 1) << kTileShift);
+      long lo = 0;
+      bool any = false;
+      for (int n = n0; n < n1; ++n) {
+        const int c = S.nbr[(size_t)(i - 1) * Np + n];
+        if (c >= 0) {
+          lo = any ? std::min(lo, (long)c - n) : (long)c - n;
+          any = true;
+        }
+      }
+      S.nbr_base[(size_t)(i - 1) * S.ntiles + t] = (int)lo;
+      for (int n = n0; n < n1; ++n) {
+        const int c = S.nbr[(size_t)(i - 1) * Np + n];
+        int16_t dd;
+        if (c >= 0) {
+          const long r = (long)c - n - lo;
+          if (r > kD16Max) {
+            fits = false;
+            break;
+          }
+          dd = (int16_t)r;
+        } else {
+          dd = (int16_t)(c == kOpen ? kD16Open : kD16Bounce);
+        }
+        S.nbr16[(size_t)(i - 1) * Np + n] = dd;
+      }
+    }
+  }
+  if (!fits) {
+    S.nbr16.clear();
+    S.nbr_base.clear();
+  }
   return contact_angles(S, wet.theta_deg, field ? wet.theta_field_deg : nullptr, &S.cos_t, &S.sin_t, &S.flags,
                         err);
 }

@@ -21,6 +21,10 @@ struct HostSetup {
   int n_fb = 0, n_in = 0, n_out = 0;
   std::vector<int> node_vox;    // [N]
   std::vector<int> nbr;         // [(Q-1) * Np]
+  // 16-bit form of nbr (see Nbr in step.hpp); empty when some offset does not fit
+  std::vector<int16_t> nbr16;   // [(Q-1) * Np]
+  std::vector<int> nbr_base;    // [(Q-1) * ntiles]
+  int ntiles = 0;
   std::vector<unsigned> flags;  // [Np]
   std::vector<int> sb_vox;      // [nsb]
   std::vector<unsigned> sb_mask;

@@ -86,9 +86,64 @@ struct Vec4T<double> {
 template <class Real>
 using Vec4 = typename Vec4T<Real>::type;
 
+// Pull table: the source node of direction i (i >= 1) of node n, or a code.
+// Stored as 16-bit deltas against a per-tile base (a tile is 256 consecutive
+// nodes; every wave lies inside one tile): s = n + base[i][tile] + d, with two
+// reserved deltas for the bounce-back and open-face codes.  Geometries whose
+// offsets do not fit use the 32-bit table instead (wide != nullptr).
+constexpr int kTileShift = 8;
+// the two codes decode by one add: kD16Bounce + kD16Code = kBounce,
+// kD16Open + kD16Code = kOpen
+constexpr int kD16Code = 32766;
+constexpr int kD16Bounce = kBounce - kD16Code;  // -32767
+constexpr int kD16Open = kOpen - kD16Code;      // -32768
+constexpr int kD16Max = 32767;
+
+struct Nbr {
+  const int16_t* d;  // [Q-1][Np]
+  const int* base;   // [Q-1][ntiles]
+  const int* wide;   // [Q-1][Np] or nullptr
+  int Np, ntiles;
+  // One entry (any node, any lane).
+  template <int i>
+  __device__ __forceinline__ int get(int n) const {
+    if (wide) return wide[(i - 1) * Np + n];
+    const int dd = d[(i - 1) * Np + n];
+    const int b = base[(i - 1) * ntiles + (n >> kTileShift)];
+    const int t = n + b + dd;
+    return dd < kD16Bounce + 1 ? dd + kD16Code : t;
+  }
+  // All Q-1 entries of node n, src[i] for i = 1..Q-1.  Every lane of the
+  // wave must ask for a node of the same tile (true for node_id() and the
+  // batched tiles, which are aligned to 64 nodes): the bases are then read
+  // once per wave, before any decode, and the decode is a select.
+  template <int Q>
+  __device__ __forceinline__ void all(int n, int* src) const {
+    if (wide) {
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        src[i] = wide[(i - 1) * Np + n];
+      });
+      return;
+    }
+    const int tile = __builtin_amdgcn_readfirstlane(n >> kTileShift);
+    int b[Q], dd[Q];
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      b[i] = base[(i - 1) * ntiles + tile];
+      dd[i] = d[(i - 1) * Np + n];
+    });
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      const int t = n + b[i] + dd[i];
+      src[i] = dd[i] < kD16Bounce + 1 ? dd[i] + kD16Code : t;
+    });
+  }
+};
+
 template <class Real>
 struct Geo {
-  const int* nbr;          // [Q-1][Np]: source of direction i (i >= 1) or a code
+  Nbr nbr;                 // pull table
   const unsigned* vf;      // [Np] voxel index | flags << kVoxBits
   const int* sb_vox;       // [nsb]
   const unsigned* sb_mask; // [nsb] bit i: the link s + e_i ends on a fluid voxel in
@@ -306,14 +361,11 @@ struct OutCompact {
 // the source is solid; open-face unknowns are left 0 for the Zou-He step).
 // The pulled loads carry no branch, so all of them are issued back to back.
 template <int D, class In, class CT>
-__device__ __forceinline__ void load_node(const In& in, const int* nbr, int Np, int n, CT* fr, CT* fx) {
+__device__ __forceinline__ void load_node(const In& in, const Nbr& nbr, int n, CT* fr, CT* fx) {
   constexpr int Q = Lat<D>::Q;
   if constexpr (In::kPull) {
     int src[Q];
-    unroll<Q - 1>([&](auto I) {
-      constexpr int i = I + 1;
-      src[i] = nbr[(i - 1) * Np + n];
-    });
+    nbr.template all<Q>(n, src);
     in.template get<0>(n, fr[0], fx[0]);
     unroll<Q - 1>([&](auto I) {
       constexpr int i = I + 1;
@@ -324,6 +376,23 @@ __device__ __forceinline__ void load_node(const In& in, const int* nbr, int Np, 
       constexpr int i = I;
       in.template get<i>(n, fr[i], fx[i]);
     });
+  }
+}
+
+// Populations of the node upstream of outlet node n (z = nz-2), pulled entry
+// by entry (that node may lie in another tile than the wave's other nodes).
+template <int D, class In, class CT>
+__device__ __forceinline__ void load_outlet_upstream(const In& in, const Nbr& nbr, int n, CT* fr, CT* fx) {
+  constexpr int Q = Lat<D>::Q;
+  if constexpr (D == 3 && In::kPull) {
+    const int u = nbr.template get<kDirZp>(n);
+    in.template get<0>(u, fr[0], fx[0]);
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      in.template get_pull<i>(nbr.template get<i>(u), u, fr[i], fx[i]);
+    });
+  } else {
+    load_node<D>(in, nbr, n, fr, fx);
   }
 }
 

@@ -286,7 +286,7 @@ class Batch:
 
     def info(self):
         n = C.c_int64()
-        bs = (C.c_int * 6)()
-        gr = (C.c_int * 6)()
+        bs = (C.c_int * 5)()
+        gr = (C.c_int * 5)()
         L.check(L.load().cg_batch_info(self._h, C.byref(n), bs, gr))
         return {"total_nodes": n.value, "block": list(bs), "grid": list(gr)}
