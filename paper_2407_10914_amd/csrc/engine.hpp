@@ -47,6 +47,10 @@ class Engine final : public EngineBase {
 
   int init(const HostSetup& S, const StepParams& P, int block, Alloc* al, hipStream_t st,
            std::string* err) override {
+    if ((double)sizeof(V4) * (double)S.V > 4294967040.0) {
+      *err = "voxel grid too large for 32-bit offsets in this precision";
+      return CG_EUNSUPPORTED;
+    }
     if (block != 0) {
       if (block != 64 && block != 128 && block != 256) {
         *err = "block must be 64, 128 or 256";

@@ -66,7 +66,38 @@ __global__ void k_phase(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
 }
 
 // ----------------------------------------------------------------- k_sb_phi
-// Eq. (34): weighted mean of the fluid link neighbours, i ascending.
+// Raw buffer loads whose out-of-range lanes return 0 without touching memory:
+// a gather over a masked subset of links with no branch per link, so all the
+// loads of a point are in flight together.  offset = kOffNone masks a lane;
+// it stays out of range for every component offset added to it (the grids
+// are below 2^32 - 256 bytes, checked when the run is created).  Vectors are
+// read component by component (x, y, z; the normal grid's w is 0): a single
+// 128-bit raw buffer load of a float4 was compiled into one dword load by the
+// toolchain in use, the per-component form is merged into dwordx3 correctly.
+constexpr uint32_t kOffNone = 0xFFFFFFC0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(uint32_t)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <class Real>
+__device__ __forceinline__ Vec4<Real> bload3(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  Vec4<Real> o;
+  o.x = bload1(r, off, Real(0));
+  o.y = bload1(r, off + (uint32_t)sizeof(Real), Real(0));
+  o.z = bload1(r, off + 2u * (uint32_t)sizeof(Real), Real(0));
+  o.w = Real(0);
+  return o;
+}
+
+// Eq. (34): weighted mean of the fluid link neighbours, i ascending (links
+// that do not end on a fluid voxel load nothing and add an exact zero).
 template <class Real, int D>
 __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int s) {
   constexpr int Q = Lat<D>::Q;
@@ -74,15 +105,21 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
+  const auto rs = grid_rsrc(R.phi, sizeof(Real) * (size_t)P.V);
+  Real ph[Q];
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    const bool on = m & (1u << i);
+    const uint32_t off = on ? (uint32_t)nb_vox<D, i>(P, ps) * (uint32_t)sizeof(Real) : kOffNone;
+    ph[i] = bload1(rs, off, Real(0));
+  });
   Real num = Real(0), den = Real(0);
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
-    if (m & (1u << i)) {
-      constexpr double w = Lat<D>::w(i);
-      const int y = nb_vox<D, i>(P, ps);
-      num = num + (Real)w * R.phi[y];
-      den = den + (Real)w;
-    }
+    constexpr double w = Lat<D>::w(i);
+    const bool on = m & (1u << i);
+    num = num + (on ? (Real)w * ph[i] : Real(0));
+    den = den + (on ? (Real)w : Real(0));
   });
   R.phi[v] = num / den;
 }
@@ -163,7 +200,8 @@ __global__ void k_normal(StepParams P, Geo<Real> G, Grids<Real> R) {
 }
 
 // ------------------------------------------------------------------- k_sb_n
-// Eq. (35): normal extrapolated to the solid boundary points, not renormalised.
+// Eq. (35): normal extrapolated to the solid boundary points, not renormalised
+// (masked buffer loads as in d_sb_phi).
 template <class Real, int D>
 __device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int s) {
   constexpr int Q = Lat<D>::Q;
@@ -171,18 +209,24 @@ __device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, 
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
+  const auto rs = grid_rsrc(R.n, sizeof(Vec4<Real>) * (size_t)P.V);
+  Vec4<Real> q[Q];
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    const bool on = m & (1u << i);
+    const uint32_t off = on ? (uint32_t)nb_vox<D, i>(P, ps) * (uint32_t)sizeof(Vec4<Real>) : kOffNone;
+    q[i] = bload3<Real>(rs, off);
+  });
   Real num[3] = {Real(0), Real(0), Real(0)};
   Real den = Real(0);
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
-    if (m & (1u << i)) {
-      constexpr double w = Lat<D>::w(i);
-      const Vec4<Real> q = R.n[nb_vox<D, i>(P, ps)];
-      const Real qq[3] = {q.x, q.y, q.z};
+    constexpr double w = Lat<D>::w(i);
+    const bool on = m & (1u << i);
+    const Real qq[3] = {q[i].x, q[i].y, q[i].z};
 #pragma unroll
-      for (int a = 0; a < D; ++a) num[a] = num[a] + (Real)w * qq[a];
-      den = den + (Real)w;
-    }
+    for (int a = 0; a < D; ++a) num[a] = num[a] + (on ? (Real)w * qq[a] : Real(0));
+    den = den + (on ? (Real)w : Real(0));
   });
   Vec4<Real> o;
   o.x = num[0] / den;
