@@ -133,6 +133,8 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   P.rho0 = o.rho0;
   P.nu_r = (tau_r - 0.5) / 3.0;
   P.nu_b = (tau_b - 0.5) / 3.0;
+  P.hinv_nu_r = (float)(0.5 / P.nu_r);
+  P.hinv_nu_b = (float)(0.5 / P.nu_b);
   for (int a = 0; a < 3; ++a) P.rg[a] = o.rho0 * b.g[a];
   if (geom->dim == 2) P.rg[2] = 0.0;
   P.rin_r = b.rho_in * b.zeta_r;

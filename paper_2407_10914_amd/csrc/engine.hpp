@@ -144,7 +144,7 @@ class Engine final : public EngineBase {
       *err = std::string("upload failed: ") + hipGetErrorString(e);
       return CG_EHIP;
     }
-    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles}, vf, sbv, sbm, nw, ct, stt};
+    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles, (int)Q - 1}, vf, sbv, sbm, nw, ct, stt};
     R_ = Grids<Real>{phi, ng, cv, fv};
     nsb_ = (int)nsb;
     dev_bytes_ = al_->total;

@@ -13,6 +13,22 @@
 namespace cg {
 
 __device__ __forceinline__ int vox_of(unsigned vf) { return (int)(vf & kVoxMask); }
+
+// Loads of per-node data that one thread reads once per kernel: marked
+// non-temporal so that they do not push the stencil neighbours' lines, which
+// several waves reuse, out of L2.
+__device__ __forceinline__ unsigned ld_once(const unsigned* p) { return __builtin_nontemporal_load(p); }
+template <class Real>
+__device__ __forceinline__ Vec4<Real> ld_once4(const Vec4<Real>* p) {
+  typedef Real v4 __attribute__((ext_vector_type(4)));
+  const v4 t = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+  Vec4<Real> o;
+  o.x = t.x;
+  o.y = t.y;
+  o.z = t.z;
+  o.w = t.w;
+  return o;
+}
 __device__ __forceinline__ unsigned flags_of(unsigned vf) { return vf >> kVoxBits; }
 
 // ------------------------------------------------------------------ k_phase
@@ -25,7 +41,7 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = double;
   if (n >= P.N) return;
-  const unsigned vf = G.vf[n];
+  const unsigned vf = ld_once(&G.vf[n]);
   const unsigned fl = flags_of(vf);
   CT phi;
   if (fl & FL_IN) {
@@ -138,7 +154,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   constexpr int Q = Lat<D>::Q;
   using CT = double;
   if (n >= P.N) return;
-  const unsigned vf = G.vf[n];
+  const unsigned vf = ld_once(&G.vf[n]);
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   const Pos ps = make_pos(P, v, fl & FL_FACE);
@@ -243,15 +259,19 @@ __global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
 
 // ------------------------------------------------------------------- k_curv
 // Curvature, Eq. (12), from the isotropic derivatives of n (same stencil as
-// Eq. 6), and the force F = 1/2 sigma kappa C (Eq. 5) + rho_o g (Eq. 36), in
-// double arithmetic for either layout.  The time step evaluates this inside
-// k_main (the force of a node is used by that node only); k_curv stores it for
-// the macroscopic fields, the observables and the adjoint.
+// Eq. 6), and the force F = 1/2 sigma kappa C (Eq. 5) + rho_o g (Eq. 36).
+// The double layout evaluates it in the order of the definition; the float
+// layout in single precision with the factor 3 folded into the stencil weights
+// (the force is ~1e-5 of a population, so its rounding stays far below the
+// single-precision tolerance).  The time step evaluates this inside k_main (the
+// force of a node is used by that node only); k_curv stores it for the
+// macroscopic fields, the observables and the adjoint.
 template <class Real, int D>
 __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real>& R, int n, int v, const Pos& ps,
                                            const Vec4<Real>& self, double* F, double& k) {
   constexpr int Q = Lat<D>::Q;
-  using CT = double;
+  constexpr bool kDev = sizeof(Real) == 4;
+  using CT = Real;
   Vec4<Real> nb[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
@@ -268,34 +288,36 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
         constexpr int i = I;
         constexpr int e = Lat<D>::e(i, b);
         if constexpr (e != 0) {
-          constexpr double we = Lat<D>::w(i) * e;
-          const Real na = a == 0 ? nb[i].x : (a == 1 ? nb[i].y : nb[i].z);
-          const CT t = (CT)we * (CT)na;
+          constexpr double we = (kDev ? 3.0 : 1.0) * Lat<D>::w(i) * e;
+          const CT na = a == 0 ? nb[i].x : (a == 1 ? nb[i].y : nb[i].z);
+          const CT t = (CT)we * na;
           s = first ? t : s + t;
           first = false;
         }
       });
-      d[b][a] = CT(3) * s;
+      d[b][a] = kDev ? s : CT(3) * s;
     });
   });
   const CT nx_ = self.x, ny_ = self.y, nz_ = self.z;
+  CT kk;
   if constexpr (D == 3) {
-    k = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (nz_ * nz_ - CT(1)) * d[2][2] +
-        (d[1][0] + d[0][1]) * nx_ * ny_ + (d[2][0] + d[0][2]) * nx_ * nz_ + (d[1][2] + d[2][1]) * nz_ * ny_;
+    kk = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (nz_ * nz_ - CT(1)) * d[2][2] +
+         (d[1][0] + d[0][1]) * nx_ * ny_ + (d[2][0] + d[0][2]) * nx_ * nz_ + (d[1][2] + d[2][1]) * nz_ * ny_;
   } else {
-    k = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (d[1][0] + d[0][1]) * nx_ * ny_;
+    kk = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (d[1][0] + d[0][1]) * nx_ * ny_;
   }
-  const Vec4<Real> c = R.c[n];
-  const CT C[3] = {(CT)c.x, (CT)c.y, (CT)c.z};
-  F[0] = F[1] = F[2] = CT(0);
+  k = (double)kk;
+  const Vec4<Real> c = ld_once4<Real>(&R.c[n]);
+  const CT C[3] = {c.x, c.y, c.z};
+  F[0] = F[1] = F[2] = 0.0;
 #pragma unroll
-  for (int a = 0; a < D; ++a) F[a] = P.half_sigma * k * C[a] + P.rg[a];
+  for (int a = 0; a < D; ++a) F[a] = (double)((CT)P.half_sigma * kk * C[a] + (CT)P.rg[a]);
 }
 
 template <class Real, int D>
 __device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, int n) {
   if (n >= P.N) return;
-  const unsigned vf = G.vf[n];
+  const unsigned vf = ld_once(&G.vf[n]);
   const int v = vox_of(vf);
   const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
   double F[3], k;
@@ -370,7 +392,7 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = double;
-  const unsigned vf = G.vf[n];
+  const unsigned vf = ld_once(&G.vf[n]);
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   Real fr[Q], fx[Q];
@@ -401,6 +423,10 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   const UT F[3] = {(UT)f4.x, (UT)f4.y, (UT)f4.z};
   const UT rho_u = kDev ? (UT)P.rho0 + (UT)drho : (UT)rho;
   UT u[3] = {UT(0), UT(0), UT(0)};
+  // single-precision step: one hardware reciprocal (about 1 ulp) for the three
+  // velocity components
+  [[maybe_unused]] UT inv_rho_u = UT(0);
+  if constexpr (kDev && Mode == MODE_STEP) inv_rho_u = __builtin_amdgcn_rcpf(rho_u);
   unroll<D>([&](auto A_) {
     constexpr int a = A_;
     UT j = UT(0);
@@ -414,11 +440,17 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
         first = false;
       }
     });
-    u[a] = (j + UT(0.5) * F[a]) / rho_u;
+    if constexpr (kDev && Mode == MODE_STEP)
+      u[a] = (j + UT(0.5) * F[a]) * inv_rho_u;
+    else
+      u[a] = (j + UT(0.5) * F[a]) / rho_u;
   });
   if constexpr (Mode == MODE_STEP) {
     Real s_nu, s_q;
-    rates(P, phi, s_nu, s_q);
+    if constexpr (kDev)
+      rates_f32(P, phi, s_nu, s_q);
+    else
+      rates(P, phi, s_nu, s_q);
     Real ur[3], Fr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -428,7 +460,7 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
     if constexpr (D == 3) {
       if (P.collision == 1) {
         if constexpr (kDev)
-          collide_mrt_fast(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
+          collide_mrt_pairs(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
         else
           collide_mrt<true>(fx, drho, (Real)P.rho0, ur, Fr, s_nu, s_q);
       } else
@@ -438,19 +470,26 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
     }
     // recolouring, Eqs. (20)-(21)
     const Real rsum = rr + rb;
-    const Real a = rr / rsum;
-    const Real b = rr * rb / rsum;
     if constexpr (kDev) {
+      // a is the red share of every population leaving the node, so it keeps
+      // the correctly rounded quotient (a biased reciprocal drifts the colour
+      // masses); b only scales the segregation term, whose weights cancel
+      const Real a = rr / rsum;
+      const Real b = rr * rb * __builtin_amdgcn_rcpf(rsum);
       const Real bb = (Real)P.beta * b;
       float4 ac;
       ac.x = a;
       ac.y = bb * n4.x;
       ac.z = bb * n4.y;
       ac.w = D == 3 ? bb * n4.z : 0.f;
-      out.AC[n] = ac;
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      const v4f acv = {ac.x, ac.y, ac.z, ac.w};
+      __builtin_nontemporal_store(acv, reinterpret_cast<v4f*>(&out.AC[n]));
 #pragma unroll
-      for (int i = 0; i < Q; ++i) out.T[i * out.Np + n] = fx[i];
+      for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(fx[i], &out.T[i * out.Np + n]);
     } else {
+      const Real a = rr / rsum;
+      const Real b = rr * rb / rsum;
       const Real nvec[3] = {n4.x, n4.y, n4.z};
       unroll<Q>([&](auto I) {
         constexpr int i = I;
@@ -584,7 +623,7 @@ __global__ void k_export(StepParams P, Geo<Real> G, Grids<Real> R, In in, double
   constexpr bool kDev = sizeof(Real) == 4;
   const int n = node_id();
   if (n >= P.N) return;
-  const unsigned vf = G.vf[n];
+  const unsigned vf = ld_once(&G.vf[n]);
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   double fr[Q], fx[Q];

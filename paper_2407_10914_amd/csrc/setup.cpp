@@ -318,7 +318,7 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
         } else {
           dd = (int16_t)(c == kOpen ? kD16Open : kD16Bounce);
         }
-        S.nbr16[(size_t)(i - 1) * Np + n] = dd;
+        S.nbr16[nbr16_index(Q - 1, i, n)] = dd;
       }
     }
   }

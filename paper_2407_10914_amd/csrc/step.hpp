@@ -66,6 +66,7 @@ struct StepParams {
   double half_sigma;  // 0.5 * sigma
   double beta, rho0;
   double nu_r, nu_b;  // (tau - 1/2)/3
+  float hinv_nu_r, hinv_nu_b;  // 1/(2 nu_r), 1/(2 nu_b) for the single-precision rates
   double rg[3];       // rho0 * g, force density of Eq. (36)
   double rin_r, rin_b;  // rho_in * zeta^r, rho_in * zeta^b
   double rho_in, rho_out, phi_in;
@@ -99,16 +100,23 @@ constexpr int kD16Bounce = kBounce - kD16Code;  // -32767
 constexpr int kD16Open = kOpen - kD16Code;      // -32768
 constexpr int kD16Max = 32767;
 
+// The deltas of the 64 nodes of one wave are stored together, direction after
+// direction ([Np/64][Q-1][64]): a wave reads its whole table row from one
+// contiguous 2.25 KiB block instead of Q-1 separate streams.
+__host__ __device__ __forceinline__ size_t nbr16_index(int qm1, int i, int n) {
+  return ((size_t)(n >> 6) * (size_t)qm1 + (size_t)(i - 1)) * 64u + (size_t)(n & 63);
+}
+
 struct Nbr {
-  const int16_t* d;  // [Q-1][Np]
+  const int16_t* d;  // [Np/64][Q-1][64], see nbr16_index
   const int* base;   // [Q-1][ntiles]
   const int* wide;   // [Q-1][Np] or nullptr
-  int Np, ntiles;
+  int Np, ntiles, qm1;
   // One entry (any node, any lane).
   template <int i>
   __device__ __forceinline__ int get(int n) const {
     if (wide) return wide[(i - 1) * Np + n];
-    const int dd = d[(i - 1) * Np + n];
+    const int dd = d[nbr16_index(qm1, i, n)];
     const int b = base[(i - 1) * ntiles + (n >> kTileShift)];
     const int t = n + b + dd;
     return dd < kD16Bounce + 1 ? dd + kD16Code : t;
@@ -131,7 +139,7 @@ struct Nbr {
     unroll<Q - 1>([&](auto I) {
       constexpr int i = I + 1;
       b[i] = base[(i - 1) * ntiles + tile];
-      dd[i] = d[(i - 1) * Np + n];
+      dd[i] = __builtin_nontemporal_load(&d[((n >> 6) * (Q - 1) + (i - 1)) * 64 + (n & 63)]);
     });
     unroll<Q - 1>([&](auto I) {
       constexpr int i = I + 1;
@@ -308,9 +316,13 @@ struct InCompact {
     constexpr double w = Lat<D>::w(i);
     constexpr int o = opp<D>(i);
     const bool fl = s >= 0;
-    const int node = fl ? s : n;
-    const int idx = fl ? i * Np + s : o * Np + n;
-    const CT t = (CT)T[idx];
+    int node = fl ? s : n;
+    int row = fl ? i * Np : o * Np;
+    // opaque to the optimiser: otherwise it turns the selects into branches
+    // (reusing the node's own (a, c) on bounce-back lanes) that wait for
+    // earlier loads before issuing the remaining gathers
+    asm("" : "+v"(node), "+v"(row));
+    const CT t = (CT)T[row + node];
     const float4 ac = AC[node];
     const CT cc[3] = {(CT)ac.y, (CT)ac.z, (CT)ac.w};
     CT ce = CT(0);
@@ -737,60 +749,135 @@ __device__ __forceinline__ void collide_mrt(CT* ft, CT drho, CT rho0, const CT* 
   });
 }
 
-// MRT collision, single-precision form: with y = f - f^eq + Fbar/2 the same
-// operator reads f'' = f + Fbar - M^-1 S M y (S vanishes on the conserved
-// moments), so only the 15 non-conserved moments of y are accumulated, one
-// population at a time, and no per-moment temporaries are kept.
+// Structure of the D3Q19 moment basis that collide_mrt_pairs relies on: the
+// rows relaxed at S_nu are even in e (equal on i and opp(i)), the rows relaxed
+// at S_q are odd, and the conserved rows are the density (all ones) and the
+// three momentum components.  With orthogonal rows the ten even rows span the
+// vectors that are even over the pairs (i, opp(i)) and the nine odd rows the
+// odd ones.
+constexpr bool mrt_pair_structure() {
+  int n1 = 0, n2 = 0;
+  for (int k = 0; k < 19; ++k) {
+    const int rc = rate_class(k);
+    n1 += rc == 1;
+    n2 += rc == 2;
+    for (int i = 1; i < 19; ++i) {
+      const int a = Mkj(k, i), b = Mkj(k, opp<3>(i));
+      if (rc == 1 && a != b) return false;
+      if (rc == 2 && a != -b) return false;
+    }
+  }
+  for (int i = 0; i < 19; ++i)
+    if (Mkj(0, i) != 1 || Mkj(3, i) != Lat<3>::e(i, 0) || Mkj(5, i) != Lat<3>::e(i, 1) ||
+        Mkj(7, i) != Lat<3>::e(i, 2))
+      return false;
+  return n1 == 9 && n2 == 6 && rate_class(0) == 0 && rate_class(3) == 0 && rate_class(5) == 0 &&
+         rate_class(7) == 0 && Mnorm2(3) == 10;
+}
+
+// MRT collision, single-precision form.  With y = f - f^eq + Fbar/2 the
+// operator of Eqs. (2)-(4) reads f'' = f + Fbar - M^-1 S M y.  Because of
+// mrt_pair_structure(), M^-1 S M y = S_nu (y_even - mean(y)) +
+// S_q (y_odd - P_j y_odd), where y_even / y_odd are the half-sums /
+// half-differences over the pairs (i, opp(i)) and P_j projects on the three
+// momentum rows (|row|^2 = 10).  That is the same linear map as the 19x19
+// transform pair, at about a third of the operations.  Per pair the
+// equilibrium and the Guo term split the same way:
+//   f^eq even = w (drho + rho0 (4.5 (e.u)^2 - 1.5 u.u)), odd = 3 w rho0 e.u;
+//   Fbar even = w (9 (e.u)(e.F) - 3 u.F),                odd = 3 w e.F.
 template <class CT>
-__device__ __forceinline__ void collide_mrt_fast(CT* g, CT drho, CT rho0, const CT* u, const CT* F, CT s_nu,
-                                                 CT s_q) {
-  constexpr int D = 3;
+__device__ __forceinline__ void collide_mrt_pairs(CT* g, CT drho, CT rho0, const CT* u, const CT* F, CT s_nu,
+                                                  CT s_q) {
+  static_assert(mrt_pair_structure(), "D3Q19 moment basis lost its even/odd structure");
   CT usq = u[0] * u[0];
   usq = usq + u[1] * u[1];
   usq = usq + u[2] * u[2];
-  CT m[19];
-  unroll<19>([&](auto K) {
-    constexpr int k = K;
-    if constexpr (rate_class(k) != 0) m[k] = CT(0);
-  });
+  CT uF = u[0] * F[0];
+  uF = uF + u[1] * F[1];
+  uF = uF + u[2] * F[2];
+  const CT a0 = drho - CT(1.5) * rho0 * usq;  // f^eq even / w without the (e.u)^2 term
+  const CT c0 = CT(-3) * uF;                  // Fbar even / w without the (e.F) term
+  const CT r45 = CT(4.5) * rho0;
+  constexpr double w0 = Lat<3>::w(0);
+  const CT fb0 = (CT)w0 * c0;
+  const CT y0 = g[0] - (CT)w0 * a0 + CT(0.5) * fb0;
+  const CT hs_nu = CT(0.5) * s_nu, hs_q = CT(0.5) * s_q;
+  // First pass, per pair leader i (i < opp(i) = o): Ye = y_i + y_o and
+  // Yo = y_i - y_o; g_i and g_o take every term that needs neither mean(y)
+  // nor the momentum of Yo, which the second pass adds.
+  CT sum = y0;
+  CT J[3] = {CT(0), CT(0), CT(0)};
   unroll<19>([&](auto I) {
     constexpr int i = I;
-    const CT y = g[i] - eq_i<D, i>(drho, rho0, u, usq) + CT(0.5) * guo_i<D, i>(u, F);
-    unroll<19>([&](auto K) {
-      constexpr int k = K;
-      constexpr int mk = Mkj(k, i);
-      if constexpr (rate_class(k) != 0 && mk != 0) {
-        if constexpr (mk == 1)
-          m[k] = m[k] + y;
-        else if constexpr (mk == -1)
-          m[k] = m[k] - y;
-        else
-          m[k] = m[k] + (CT)mk * y;
-      }
-    });
+    constexpr int o = opp<3>(i);
+    if constexpr (i > 0 && o > i) {
+      constexpr double w = Lat<3>::w(i);
+      CT eu = CT(0), eF = CT(0);
+      bool first = true;
+      unroll<3>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<3>::e(i, a);
+        if constexpr (e != 0) {
+          const CT tu = e == 1 ? u[a] : -u[a];
+          const CT tF = e == 1 ? F[a] : -F[a];
+          eu = first ? tu : eu + tu;
+          eF = first ? tF : eF + tF;
+          first = false;
+        }
+      });
+      const CT eqe = (CT)w * (a0 + r45 * eu * eu);
+      const CT eqo = (CT)(3.0 * w) * rho0 * eu;
+      const CT Be = (CT)w * (c0 + CT(9) * eu * eF);
+      const CT Bo = (CT)(3.0 * w) * eF;
+      const CT gi = g[i], go = g[o];
+      const CT Ye = (gi + go) - CT(2) * eqe + Be;
+      const CT Yo = (gi - go) - CT(2) * eqo + Bo;
+      sum = sum + Ye;
+      unroll<3>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<3>::e(i, a);
+        if constexpr (e == 1) J[a] = J[a] + Yo;
+        if constexpr (e == -1) J[a] = J[a] - Yo;
+      });
+      const CT E = hs_nu * Ye, O = hs_q * Yo;
+      g[i] = gi + (Be + Bo) - (E + O);
+      g[o] = go + (Be - Bo) - (E - O);
+    }
   });
-  unroll<19>([&](auto K) {
-    constexpr int k = K;
-    constexpr int rc = rate_class(k);
-    if constexpr (rc != 0) m[k] = m[k] * ((rc == 1 ? s_nu : s_q) * (CT)(1.0 / (double)Mnorm2(k)));
-  });
+  // Second pass: the density and momentum projections,
+  // +S_nu mean(y) on every population, +-S_q (e_i.J)/10 on each pair.
+  const CT ybar = sum * CT(1.0 / 19.0);
+  const CT cn = s_nu * ybar;
+  const CT Jq[3] = {J[0] * (CT(0.1) * s_q), J[1] * (CT(0.1) * s_q), J[2] * (CT(0.1) * s_q)};
+  g[0] = g[0] + fb0 - s_nu * (y0 - ybar);
   unroll<19>([&](auto I) {
     constexpr int i = I;
-    CT s = guo_i<D, i>(u, F);
-    unroll<19>([&](auto K) {
-      constexpr int k = K;
-      constexpr int mk = Mkj(k, i);
-      if constexpr (rate_class(k) != 0 && mk != 0) {
-        if constexpr (mk == 1)
-          s = s - m[k];
-        else if constexpr (mk == -1)
-          s = s + m[k];
-        else
-          s = s - (CT)mk * m[k];
-      }
-    });
-    g[i] = g[i] + s;
+    constexpr int o = opp<3>(i);
+    if constexpr (i > 0 && o > i) {
+      CT eJ = CT(0);
+      bool first = true;
+      unroll<3>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<3>::e(i, a);
+        if constexpr (e != 0) {
+          const CT t = e == 1 ? Jq[a] : -Jq[a];
+          eJ = first ? t : eJ + t;
+          first = false;
+        }
+      });
+      g[i] = g[i] + (cn + eJ);
+      g[o] = g[o] + (cn - eJ);
+    }
   });
+}
+
+// Rates of Eqs. (13)-(16), single-precision path: the same expressions
+// rearranged to two hardware reciprocals (about 1 ulp each),
+// 1/nu = (1 + phi)/(2 nu_r) + (1 - phi)/(2 nu_b), S_nu = (1/nu) / (3 + (1/nu)/2).
+__device__ __forceinline__ void rates_f32(const StepParams& P, float phi, float& s_nu, float& s_q) {
+  const float inv_nu = (1.f + phi) * P.hinv_nu_r + (1.f - phi) * P.hinv_nu_b;
+  s_nu = inv_nu * __builtin_amdgcn_rcpf(3.f + 0.5f * inv_nu);
+  s_q = (8.f * (2.f - s_nu)) * __builtin_amdgcn_rcpf(8.f - s_nu);
 }
 
 // Single-relaxation-time collision with Guo forcing:
