@@ -297,16 +297,65 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   const CT ra = rr / rho;
   const CT rbb = rr * rb / rho;
 
-  // ---- pass 1
+  // ---- y = f - f^eq + Fbar/2 per direction and, for MRT, its projections.
+  // The relaxation part of the MRT operator is R = M^-1 S M =
+  // S_nu P_e + S_q P_o (see collide_mrt_pairs): P_e takes the half-sum over a
+  // pair (i, opp(i)) minus the mean over all 19, P_o the half-difference minus
+  // the projection on the momentum rows.  Both are symmetric projections, so
+  // R^T = R; the adjoint needs dl.R y (for lambda a), mu.P_e y and mu.P_o y
+  // (the rates) and R mu (the adjoint of y).  Ey[L] / Oy[L] hold (P_e y) and
+  // (P_o y) at the pair leader L = min(i, opp(i)); (P_o y) changes sign on the
+  // partner.
+  // bg_i = f_i + Fbar_i, the factor of the recolouring adjoint in lambda a
+  CT yv[Q], bg[Q];
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    constexpr double w = Lat<D>::w(i);
+    const CT gu = guo_i<D, i>(u, F);
+    yv[i] = x[i] - eq_i<D, i>(drho, rho0, u, usq) + CT(0.5) * gu;
+    bg[i] = (kDev ? (CT)w * rho0 + x[i] : x[i]) + gu;
+  });
+  CT Ey[kMrt ? Q : 1], Oy[kMrt ? Q : 1];
+  if constexpr (kMrt) {
+    static_assert(mrt_pair_structure(), "D3Q19 moment basis lost its even/odd structure");
+    CT sy = yv[0];
+    CT Jy[3] = {CT(0), CT(0), CT(0)};
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int o = opp<D>(i);
+      if constexpr (i > 0 && o > i) {
+        sy = sy + (yv[i] + yv[o]);
+        unroll<3>([&](auto A_) {
+          constexpr int a = A_;
+          constexpr int e = Lat<D>::e(i, a);
+          if constexpr (e == 1) Jy[a] = Jy[a] + (yv[i] - yv[o]);
+          if constexpr (e == -1) Jy[a] = Jy[a] - (yv[i] - yv[o]);
+        });
+      }
+    });
+    const CT ybar = sy * CT(1.0 / 19.0);
+    Ey[0] = yv[0] - ybar;
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int o = opp<D>(i);
+      if constexpr (i > 0 && o > i) {
+        CT eJ = CT(0);
+        unroll<3>([&](auto A_) {
+          constexpr int a = A_;
+          constexpr int e = Lat<D>::e(i, a);
+          if constexpr (e == 1) eJ = eJ + Jy[a];
+          if constexpr (e == -1) eJ = eJ - Jy[a];
+        });
+        Ey[i] = CT(0.5) * (yv[i] + yv[o]) - ybar;
+        Oy[i] = CT(0.5) * (yv[i] - yv[o]) - CT(0.1) * eJ;
+      }
+    });
+  }
+  // ---- pass 1: the adjoint arriving from t+1 along the reversed pull
   CT mu[Q];
   CT a1 = CT(0), lb = CT(0), lnr[3] = {CT(0), CT(0), CT(0)};
-  CT my[19], md[19], nu[19];  // moments of y, delta, mu (non-conserved rows; BGK uses slot 0)
-#pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    my[k] = CT(0);
-    md[k] = CT(0);
-    nu[k] = CT(0);
-  }
+  CT dRy = CT(0), mPe = CT(0), mPo = CT(0);  // MRT: dl.R y, mu.P_e y, mu.P_o y
+  CT my0 = CT(0), md0 = CT(0);               // BGK: mu.y, y.dl
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     constexpr double w = Lat<D>::w(i);
@@ -321,32 +370,34 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
       } else {
         constexpr int o = opp<D>(i);
         const int s = src[o];  // node at x - e_o = x + e_i
-        li = s >= 0 ? i * P.Np + s : o * P.Np + n;
         ri = s >= 0 ? s : n;
+        int row = s >= 0 ? i * P.Np : o * P.Np;
+        // opaque to the optimiser, which would otherwise split the selects
+        // into branches that wait for earlier loads
+        asm("" : "+v"(ri), "+v"(row));
+        li = row + ri;
       }
       const CT l = A.lf_in[li];
       const Vec2<Real> r = A.lr[ri];
       dl = (CT)r.x - (CT)r.y;
       m = l + (CT)r.y + ra * dl;
     }
-    const CT fe = eq_i<D, i>(drho, rho0, u, usq);
-    const CT gu = guo_i<D, i>(u, F);
-    const CT y = x[i] - fe + CT(0.5) * gu;
-    const CT base = kDev ? (CT)w * rho0 + x[i] : x[i];
-    a1 = a1 + (base + gu) * dl;
+    a1 = a1 + bg[i] * dl;
     if constexpr (kMrt) {
-      unroll<19>([&](auto K) {
-        constexpr int k = K;
-        constexpr int mk = Mkj(k, i);
-        if constexpr (rate_class(k) != 0 && mk != 0) {
-          my[k] = my[k] + (CT)mk * y;
-          md[k] = md[k] + (CT)mk * dl;
-          nu[k] = nu[k] + (CT)mk * m;
-        }
-      });
+      constexpr int L = i < opp<D>(i) ? i : opp<D>(i);
+      const CT pe = Ey[L];
+      if constexpr (i == 0) {
+        dRy = dRy + s_nu * pe * dl;
+        mPe = mPe + m * pe;
+      } else {
+        const CT po = i == L ? Oy[L] : -Oy[L];
+        dRy = dRy + (s_nu * pe + s_q * po) * dl;
+        mPe = mPe + m * pe;
+        mPo = mPo + m * po;
+      }
     } else {
-      md[0] = md[0] + y * dl;
-      my[0] = my[0] + m * y;
+      md0 = md0 + yv[i] * dl;
+      my0 = my0 + m * yv[i];
     }
     mu[i] = m;
     if constexpr (i > 0) {
@@ -367,75 +418,112 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
       });
     }
   });
-  // ---- lambda a and the rate adjoints
-  CT la, lsnu = CT(0), lsq = CT(0);
+  // ---- lambda a, the rate adjoints and R mu
+  CT la, lsnu, lsq = CT(0);
+  CT lyv[kMrt ? Q : 1];
   if constexpr (kMrt) {
-    la = a1;
-    {
-      unroll<19>([&](auto K) {
-        constexpr int k = K;
-        constexpr int rc = rate_class(k);
-        if constexpr (rc != 0) {
-          constexpr CT inorm = (CT)(1.0 / (double)Mnorm2(k));
-          const CT S = rc == 1 ? s_nu : s_q;
-          la = la - S * inorm * my[k] * md[k];
-          if constexpr (rc == 1)
-            lsnu = lsnu - nu[k] * inorm * my[k];
-          else
-            lsq = lsq - nu[k] * inorm * my[k];
-          nu[k] = S * inorm * nu[k];
-        }
-      });
-    }
+    la = a1 - dRy;
+    lsnu = -mPe;
+    lsq = -mPo;
+    CT sm = mu[0];
+    CT Jm[3] = {CT(0), CT(0), CT(0)};
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int o = opp<D>(i);
+      if constexpr (i > 0 && o > i) {
+        sm = sm + (mu[i] + mu[o]);
+        unroll<3>([&](auto A_) {
+          constexpr int a = A_;
+          constexpr int e = Lat<D>::e(i, a);
+          if constexpr (e == 1) Jm[a] = Jm[a] + (mu[i] - mu[o]);
+          if constexpr (e == -1) Jm[a] = Jm[a] - (mu[i] - mu[o]);
+        });
+      }
+    });
+    const CT mbar = sm * CT(1.0 / 19.0);
+    lyv[0] = -s_nu * (mu[0] - mbar);
+    unroll<Q>([&](auto I) {
+      constexpr int i = I;
+      constexpr int o = opp<D>(i);
+      if constexpr (i > 0 && o > i) {
+        CT eJ = CT(0);
+        unroll<3>([&](auto A_) {
+          constexpr int a = A_;
+          constexpr int e = Lat<D>::e(i, a);
+          if constexpr (e == 1) eJ = eJ + Jm[a];
+          if constexpr (e == -1) eJ = eJ - Jm[a];
+        });
+        const CT Em = CT(0.5) * (mu[i] + mu[o]) - mbar;
+        const CT Om = CT(0.5) * (mu[i] - mu[o]) - CT(0.1) * eJ;
+        lyv[i] = -(s_nu * Em + s_q * Om);
+        lyv[o] = -(s_nu * Em - s_q * Om);
+      }
+    });
   } else {
-    la = a1 - s_nu * md[0];
-    lsnu = -my[0];
+    la = a1 - s_nu * md0;
+    lsnu = -my0;
   }
-  // ---- pass 2
+  // ---- pass 2: adjoints of f^eq and Fbar with respect to rho, u and F.
+  // With qe_i = w_i rho0 lambda_feq,i and qg_i = w_i lambda_Fbar,i,
+  //   lambda u = sum_i e_i [3 qe_i + 9 (qe_i e_i.u + qg_i e_i.F)] - 3 u sum qe - 3 F sum qg,
+  //   lambda F = sum_i e_i [3 qg_i + 9 qg_i e_i.u]                 - 3 u sum qg,
+  // (f^eq_i = w [drho + rho0 (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)],
+  //  Fbar_i = w [3 (e - u).F + 9 (e.u)(e.F)]), so each direction adds two
+  // scalars along e_i.
   CT lrho = CT(0), lu[3] = {CT(0), CT(0), CT(0)}, lF[3] = {CT(0), CT(0), CT(0)};
+  CT sqe = CT(0), sqg = CT(0);
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     constexpr double w = Lat<D>::w(i);
     CT ly;
     if constexpr (kMrt) {
-      CT t = CT(0);
-      unroll<19>([&](auto K) {
-        constexpr int k = K;
-        constexpr int mk = Mkj(k, i);
-        if constexpr (rate_class(k) != 0 && mk != 0) t = t + (CT)mk * nu[k];
-      });
-      ly = -t;
+      ly = lyv[i];
     } else {
       ly = -s_nu * mu[i];
     }
     const CT lfe = -ly;
     const CT lgu = mu[i] + CT(0.5) * ly;
-    CT eu = CT(0), eF = CT(0);
-    unroll<D>([&](auto A_) {
-      constexpr int a = A_;
-      constexpr int e = Lat<D>::e(i, a);
-      if constexpr (e == 1) {
-        eu = eu + u[a];
-        eF = eF + F[a];
-      }
-      if constexpr (e == -1) {
-        eu = eu - u[a];
-        eF = eF - F[a];
-      }
-    });
-    // f^eq_i = w [rho + rho0 (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]
     lrho = lrho + (CT)w * lfe;
     const CT qe = (CT)w * lfe * rho0;
-    // Fbar_i = w [3 (e - u).F + 9 (e.u)(e.F)]
     const CT qg = (CT)w * lgu;
-    unroll<D>([&](auto A_) {
-      constexpr int a = A_;
-      constexpr CT e = (CT)Lat<D>::e(i, a);
-      lu[a] = lu[a] + qe * (CT(3) * e + CT(9) * eu * e - CT(3) * u[a]) + qg * (CT(-3) * F[a] + CT(9) * eF * e);
-      lF[a] = lF[a] + qg * (CT(3) * (e - u[a]) + CT(9) * eu * e);
-    });
+    sqe = sqe + qe;
+    sqg = sqg + qg;
+    if constexpr (i > 0) {
+      CT eu = CT(0), eF = CT(0);
+      unroll<D>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<D>::e(i, a);
+        if constexpr (e == 1) {
+          eu = eu + u[a];
+          eF = eF + F[a];
+        }
+        if constexpr (e == -1) {
+          eu = eu - u[a];
+          eF = eF - F[a];
+        }
+      });
+      const CT Au = CT(3) * qe + CT(9) * (qe * eu + qg * eF);
+      const CT AF = CT(3) * qg + CT(9) * qg * eu;
+      unroll<D>([&](auto A_) {
+        constexpr int a = A_;
+        constexpr int e = Lat<D>::e(i, a);
+        if constexpr (e == 1) {
+          lu[a] = lu[a] + Au;
+          lF[a] = lF[a] + AF;
+        }
+        if constexpr (e == -1) {
+          lu[a] = lu[a] - Au;
+          lF[a] = lF[a] - AF;
+        }
+      });
+    }
     mu[i] = mu[i] + ly;  // lambda f_i (total) before the velocity term
   });
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lu[a] = lu[a] - CT(3) * (u[a] * sqe + F[a] * sqg);
+    lF[a] = lF[a] - CT(3) * u[a] * sqg;
+  }
   // rates, Eqs. (13)-(16): S_nu(phi), S_q(S_nu)
   {
     const CT inv_nu = (CT(1) + phi) / (CT(2) * (CT)P.nu_r) + (CT(1) - phi) / (CT(2) * (CT)P.nu_b);

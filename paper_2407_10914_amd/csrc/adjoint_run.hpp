@@ -121,8 +121,11 @@ class AdjointRun {
   void fstep(const In& in, const Slot& out, int64_t k = -1) {
     auto o = out_of<D>(out);
     const Grids<Real> saved = E.R_;
-    if (k >= 0 && !fg_.empty()) E.R_ = fg_[(size_t)k];
-    E.template front_with<D>(in, 5);
+    const bool keep = k >= 0 && !fg_.empty();
+    if (keep) E.R_ = fg_[(size_t)k];
+    // the stored force and curvature are needed only by a reverse step that
+    // will use this front; k_main evaluates its own otherwise
+    E.template front_with<D>(in, keep ? 5 : 4);
     E.template launch_main<D>(in, o);
     E.R_ = saved;
   }

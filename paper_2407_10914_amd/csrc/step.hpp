@@ -100,15 +100,17 @@ constexpr int kD16Bounce = kBounce - kD16Code;  // -32767
 constexpr int kD16Open = kOpen - kD16Code;      // -32768
 constexpr int kD16Max = 32767;
 
-// The deltas of the 64 nodes of one wave are stored together, direction after
-// direction ([Np/64][Q-1][64]): a wave reads its whole table row from one
-// contiguous 2.25 KiB block instead of Q-1 separate streams.
+// The deltas of the 64 nodes of one wave are stored together, two directions
+// per 32-bit word ([Np/64][(Q-1)/2][64] words; direction 2k+1 in the low half,
+// 2k+2 in the high half): a wave reads its whole table row with (Q-1)/2 loads
+// from one contiguous block instead of Q-1 separate streams.
 __host__ __device__ __forceinline__ size_t nbr16_index(int qm1, int i, int n) {
-  return ((size_t)(n >> 6) * (size_t)qm1 + (size_t)(i - 1)) * 64u + (size_t)(n & 63);
+  const size_t word = ((size_t)(n >> 6) * (size_t)(qm1 / 2) + (size_t)((i - 1) >> 1)) * 64u + (size_t)(n & 63);
+  return 2u * word + (size_t)((i - 1) & 1);
 }
 
 struct Nbr {
-  const int16_t* d;  // [Np/64][Q-1][64], see nbr16_index
+  const int16_t* d;  // [Np/64][(Q-1)/2][64][2], see nbr16_index
   const int* base;   // [Q-1][ntiles]
   const int* wide;   // [Q-1][Np] or nullptr
   int Np, ntiles, qm1;
@@ -134,12 +136,19 @@ struct Nbr {
       });
       return;
     }
+    static_assert((Q - 1) % 2 == 0, "pull-table words hold two directions");
     const int tile = __builtin_amdgcn_readfirstlane(n >> kTileShift);
     int b[Q], dd[Q];
+    const int* dw = reinterpret_cast<const int*>(d);
+    unroll<(Q - 1) / 2>([&](auto K) {
+      constexpr int k = K;
+      const int wv = __builtin_nontemporal_load(&dw[((n >> 6) * ((Q - 1) / 2) + k) * 64 + (n & 63)]);
+      dd[2 * k + 1] = (int)(int16_t)(wv & 0xffff);
+      dd[2 * k + 2] = wv >> 16;
+    });
     unroll<Q - 1>([&](auto I) {
       constexpr int i = I + 1;
       b[i] = base[(i - 1) * ntiles + tile];
-      dd[i] = __builtin_nontemporal_load(&d[((n >> 6) * (Q - 1) + (i - 1)) * 64 + (n & 63)]);
     });
     unroll<Q - 1>([&](auto I) {
       constexpr int i = I + 1;
@@ -283,10 +292,23 @@ struct InCanon {
 template <int D>
 struct InCompact {
   static constexpr bool kPull = true;
+  static constexpr bool kSplitRest = true;
   const float* T;
   const float4* AC;
   int Np;
   float rho0;
+  // The rest population of node n (get<0>) split into its two loads and its
+  // arithmetic, so that load_node can issue the loads ahead of the pull table.
+  struct Rest {
+    float t, a;
+  };
+  __device__ __forceinline__ Rest load_rest(int n) const { return Rest{T[n], AC[n].x}; }
+  template <class CT>
+  __device__ __forceinline__ void finish_rest(const Rest& q, CT& r, CT& x) const {
+    const CT t = (CT)q.t;
+    r = (CT)q.a * ((CT)Lat<D>::w(0) * (CT)rho0 + t);
+    x = t;
+  }
   template <int i, class CT>
   __device__ __forceinline__ void get(int s, CT& r, CT& x) const {
     constexpr double w = Lat<D>::w(i);
@@ -310,10 +332,14 @@ struct InCompact {
   // pulled direction i >= 1 of node n with pull-table entry s (see load_node):
   // the same value as get<i>(s) from a fluid source, get<opp(i)>(n) for a
   // bounce-back link (the rebuilt red term changes sign with e), 0 for an open
-  // face, without a branch
-  template <int i, class CT>
-  __device__ __forceinline__ void get_pull(int s, int n, CT& r, CT& x) const {
-    constexpr double w = Lat<D>::w(i);
+  // face, without a branch.  load_pull issues the two loads, finish_pull does
+  // the arithmetic; get_pull is both.
+  struct Raw {
+    float t;
+    float4 ac;
+  };
+  template <int i>
+  __device__ __forceinline__ Raw load_pull(int s, int n) const {
     constexpr int o = opp<D>(i);
     const bool fl = s >= 0;
     int node = fl ? s : n;
@@ -322,20 +348,28 @@ struct InCompact {
     // (reusing the node's own (a, c) on bounce-back lanes) that wait for
     // earlier loads before issuing the remaining gathers
     asm("" : "+v"(node), "+v"(row));
-    const CT t = (CT)T[row + node];
-    const float4 ac = AC[node];
-    const CT cc[3] = {(CT)ac.y, (CT)ac.z, (CT)ac.w};
-    CT ce = CT(0);
-    unroll<D>([&](auto A_) {
-      constexpr int d = A_;
-      constexpr int e = Lat<D>::e(i, d);
-      if constexpr (e == 1) ce = ce + cc[d];
-      if constexpr (e == -1) ce = ce - cc[d];
-    });
+    return Raw{T[row + node], AC[node]};
+  }
+  template <int i, class CT>
+  __device__ __forceinline__ void finish_pull(const Raw& q, int s, CT& r, CT& x) const {
+    constexpr double w = Lat<D>::w(i);
+    const bool fl = s >= 0;
+    const CT t = (CT)q.t;
+    const float4 ac = q.ac;
+    // every component of c enters, the ones along which e_i is 0 with a zero
+    // factor (which cannot be folded away): the record is then read by one
+    // 16-byte load instead of two or three narrower ones, which keeps the
+    // loads of a node within the hardware's count of loads in flight
+    CT ce = (CT)(float)Lat<D>::e(i, 0) * (CT)ac.y + (CT)(float)Lat<D>::e(i, 1) * (CT)ac.z;
+    if constexpr (D == 3) ce = ce + (CT)(float)Lat<D>::e(i, 2) * (CT)ac.w;
     const CT r0 = (CT)ac.x * ((CT)w * (CT)rho0 + t) + (CT)w * (fl ? ce : -ce);
     const bool open = s < kBounce;
     r = open ? CT(0) : r0;
     x = open ? CT(0) : t;
+  }
+  template <int i, class CT>
+  __device__ __forceinline__ void get_pull(int s, int n, CT& r, CT& x) const {
+    finish_pull<i>(load_pull<i>(s, n), s, r, x);
   }
 };
 
@@ -368,6 +402,20 @@ struct OutCompact {
   int Np;
 };
 
+template <class In>
+constexpr auto requires_split_rest(int) -> decltype(In::kSplitRest, bool()) {
+  return true;
+}
+template <class In>
+constexpr bool requires_split_rest(long) {
+  return false;
+}
+template <class In>
+constexpr bool split_rest() {
+  if constexpr (requires_split_rest<In>(0)) return In::kSplitRest;
+  return false;
+}
+
 // Gather the pre-collision populations of node n (pull streaming with halfway
 // bounce-back: f_i(x) = f'_i(x - e_i) from a fluid source, f'_opp(i)(x) when
 // the source is solid; open-face unknowns are left 0 for the Zou-He step).
@@ -377,12 +425,33 @@ __device__ __forceinline__ void load_node(const In& in, const Nbr& nbr, int n, C
   constexpr int Q = Lat<D>::Q;
   if constexpr (In::kPull) {
     int src[Q];
-    nbr.template all<Q>(n, src);
-    in.template get<0>(n, fr[0], fx[0]);
-    unroll<Q - 1>([&](auto I) {
-      constexpr int i = I + 1;
-      in.template get_pull<i>(src[i], n, fr[i], fx[i]);
-    });
+    if constexpr (split_rest<In>()) {
+      // the rest population's loads first, kept there by a scheduling
+      // barrier (otherwise they sink below the gathers and add a round trip)
+      const auto q = in.load_rest(n);
+      __builtin_amdgcn_sched_barrier(0);
+      nbr.template all<Q>(n, src);
+      // all gathers issued before any is used (a use in between waits for
+      // every older load, which splits the gather into several round trips)
+      typename In::Raw raw[Q];
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        raw[i] = in.template load_pull<i>(src[i], n);
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        in.template finish_pull<i>(raw[i], src[i], fr[i], fx[i]);
+      });
+      in.finish_rest(q, fr[0], fx[0]);
+    } else {
+      nbr.template all<Q>(n, src);
+      in.template get<0>(n, fr[0], fx[0]);
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        in.template get_pull<i>(src[i], n, fr[i], fx[i]);
+      });
+    }
   } else {
     unroll<Q>([&](auto I) {
       constexpr int i = I;
