@@ -87,7 +87,7 @@ __global__ void k_phase(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
 // loads of a point are in flight together.  offset = kOffNone masks a lane;
 // it stays out of range for every component offset added to it (the grids
 // are below 2^32 - 256 bytes, checked when the run is created).  Vectors are
-// read component by component (x, y, z; the normal grid's w is 0): a single
+// read component by component (x, y, z; w is not needed there): a single
 // 128-bit raw buffer load of a float4 was compiled into one dword load by the
 // toolchain in use, the per-component form is merged into dwordx3 correctly.
 constexpr uint32_t kOffNone = 0xFFFFFFC0u;
@@ -307,6 +307,8 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
     kk = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (d[1][0] + d[0][1]) * nx_ * ny_;
   }
   k = (double)kk;
+  // C as stored by k_normal: rebuilding it as |C| n in single precision
+  // triples its rounding, which the force passes straight to the velocity
   const Vec4<Real> c = ld_once4<Real>(&R.c[n]);
   const CT C[3] = {c.x, c.y, c.z};
   F[0] = F[1] = F[2] = 0.0;
@@ -402,7 +404,16 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   }
   Real rr, rb, rho, drho;
   node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
-  const Real phi = R.phi[v];
+  Real phi;
+  if constexpr (kDev && Mode == MODE_STEP) {
+    // the phase of this node from the densities just pulled (k_phase stored
+    // the same value, summed in double); Zou-He nodes keep the stored one,
+    // which the boundary condition imposes
+    phi = (rr - rb) * __builtin_amdgcn_rcpf(rho);
+    if (fl & (FL_IN | FL_OUT)) phi = R.phi[v];
+  } else {
+    phi = R.phi[v];
+  }
   const Vec4<Real> n4 = R.n[v];
   Vec4<Real> f4;
   if constexpr (Mode == MODE_STEP) {
@@ -471,10 +482,21 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
     // recolouring, Eqs. (20)-(21)
     const Real rsum = rr + rb;
     if constexpr (kDev) {
-      // a is the red share of every population leaving the node, so it keeps
-      // the correctly rounded quotient (a biased reciprocal drifts the colour
-      // masses); b only scales the segregation term, whose weights cancel
-      const Real a = rr / rsum;
+      // a is the red share of every population leaving the node: the red
+      // density pulled in and the post-collision total that the next pull
+      // rebuilds from g'' (single-precision weights, as in InCompact) are
+      // summed in double, and a is their correctly rounded quotient, so the
+      // red mass leaving equals the red mass that arrived up to the rounding
+      // of a (single-precision sums drifted the colour masses by ~1e-9 per
+      // step while interfaces move).  b only scales the segregation term,
+      // whose weights cancel.
+      double rrd = 0.0, td = 0.0;
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        rrd = rrd + (double)fr[i];
+        td = td + ((double)((float)Lat<D>::w(i) * (float)P.rho0) + (double)fx[i]);
+      });
+      const Real a = (Real)(rrd / td);
       const Real b = rr * rb * __builtin_amdgcn_rcpf(rsum);
       const Real bb = (Real)P.beta * b;
       float4 ac;
