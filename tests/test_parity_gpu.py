@@ -154,14 +154,18 @@ def test_fp32_per_step_drop_periodic():
 
 
 def test_fp32_mass_conservation_periodic_drop():
+    """Per-colour mass over the whole relaxation of a drop (4000 steps: the
+    interface moves for ~3000), where rounding biases of the recolouring
+    would accumulate."""
     case, kw = drop_3d(n=24, R=7.0)
     g = _sim(case, kw, "f32")
     a = g.observe()
-    g.step(1000)
-    b = g.observe()
-    _say("fp32 mass", b["mass_r"] / a["mass_r"] - 1, b["mass_b"] / a["mass_b"] - 1)
-    assert abs(b["mass_r"] / a["mass_r"] - 1) <= 1e-6
-    assert abs(b["mass_b"] / a["mass_b"] - 1) <= 1e-6
+    for T in (1000, 1000, 2000):
+        g.step(T)
+        b = g.observe()
+        _say("fp32 mass", b["mass_r"] / a["mass_r"] - 1, b["mass_b"] / a["mass_b"] - 1)
+        assert abs(b["mass_r"] / a["mass_r"] - 1) <= 1e-6
+        assert abs(b["mass_b"] / a["mass_b"] - 1) <= 1e-6
 
 
 def test_fp64_mass_conservation_and_oracle_observables_periodic_drop():
