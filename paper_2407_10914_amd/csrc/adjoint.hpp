@@ -649,13 +649,31 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
   const Pos ps = make_pos(P, v, face);
   CT acc[3] = {CT(0), CT(0), CT(0)};
   CT d[3][3] = {{CT(0), CT(0), CT(0)}, {CT(0), CT(0), CT(0)}, {CT(0), CT(0), CT(0)}};
+  // a solid boundary point gathers from its fluid links only (lambda kappa is
+  // zero on every other voxel, so the skipped terms are exact zeros): masked
+  // buffer loads, all in flight together
+  [[maybe_unused]] unsigned msk = 0;
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t rn, rk;
+  if constexpr (kSb) {
+    msk = G.sb_mask[idx];
+    rn = grid_rsrc(R.n, sizeof(Vec4<Real>) * (size_t)P.V);
+    rk = grid_rsrc(A.lk, sizeof(Real) * (size_t)P.V);
+  }
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
     constexpr double w = Lat<D>::w(j);
     const int x = nb_vox<D, j>(P, ps);
-    const Vec4<Real> q = R.n[x];
+    Vec4<Real> q;
+    CT lk;
+    if constexpr (kSb) {
+      const bool on = msk & (1u << j);
+      q = bload3<Real>(rn, on ? (uint32_t)x * (uint32_t)sizeof(Vec4<Real>) : kOffNone);
+      lk = bload1(rk, on ? (uint32_t)x * (uint32_t)sizeof(Real) : kOffNone, Real(0));
+    } else {
+      q = R.n[x];
+      lk = (CT)A.lk[x];
+    }
     const CT nq[3] = {(CT)q.x, (CT)q.y, (CT)q.z};
-    const CT lk = (CT)A.lk[x];
     CT en = CT(0);
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
@@ -853,13 +871,41 @@ __device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Re
   return acc;
 }
 
+// The same at a solid boundary point, over its fluid links only: lambda C is
+// written on fluid voxels alone (zero elsewhere), so the skipped terms are
+// exact zeros; masked buffer loads keep every gather in flight together.
+template <class Real, int D>
+__device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs<Real>& A, const Pos& ps,
+                                              unsigned msk) {
+  constexpr int Q = Lat<D>::Q;
+  const auto rc = grid_rsrc(A.lc, sizeof(Vec4<Real>) * (size_t)P.V);
+  Real acc = Real(0);
+  unroll<Q - 1>([&](auto J) {
+    constexpr int j = J + 1;
+    const bool on = msk & (1u << j);
+    const Vec4<Real> q =
+        bload3<Real>(rc, on ? (uint32_t)nb_vox<D, j>(P, ps) * (uint32_t)sizeof(Vec4<Real>) : kOffNone);
+    const Real qq[3] = {q.x, q.y, q.z};
+    Real t = Real(0);
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr int e = Lat<D>::e(j, a);
+      if constexpr (e == 1) t = t + qq[a];
+      if constexpr (e == -1) t = t - qq[a];
+    });
+    acc = acc + (Real)(-3.0 * Lat<D>::w(j)) * t;
+  });
+  return acc;
+}
+
 template <class Real, int D>
 __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   const int s = node_id();
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
-  const Pos ps = make_pos(P, v, G.sb_mask[s] & 1u);
-  A.lphi[v] = adj_grad_t<Real, D>(P, A, ps) * A.iden[v];
+  const unsigned m = G.sb_mask[s];
+  const Pos ps = make_pos(P, v, m & 1u);
+  A.lphi[v] = adj_grad_t_sb<Real, D>(P, A, ps, m) * A.iden[v];
 }
 
 template <class Real, int D>

@@ -123,10 +123,10 @@ class AdjointRun {
     const Grids<Real> saved = E.R_;
     const bool keep = k >= 0 && !fg_.empty();
     if (keep) E.R_ = fg_[(size_t)k];
-    // the stored force and curvature are needed only by a reverse step that
-    // will use this front; k_main evaluates its own otherwise
-    E.template front_with<D>(in, keep ? 5 : 4);
-    E.template launch_main<D>(in, o);
+    // k_main evaluates the force and curvature itself; a kept front also
+    // gets them stored, for the reverse step
+    E.template front_with<D>(in, 4);
+    E.template launch_main<D>(in, o, keep ? (void*)E.R_.f : nullptr);
     E.R_ = saved;
   }
 

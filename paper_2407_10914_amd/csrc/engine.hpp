@@ -576,19 +576,18 @@ class Engine final : public EngineBase {
 
   // the step kernel at the tuned block size (its launch bounds follow it)
   template <int D, class In, class Out>
-  void launch_main(const In& in, const Out& out) {
+  void launch_main(const In& in, const Out& out, void* fstore = nullptr) {
+    MacroOut mo{};
+    mo.fstore = fstore;
     switch (bs_[K_MAIN]) {
       case 64:
-        launch_bs(K_MAIN, 64, k_main<Real, D, 64, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, MacroOut{},
-                  ObsOut{});
+        launch_bs(K_MAIN, 64, k_main<Real, D, 64, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, mo, ObsOut{});
         break;
       case 128:
-        launch_bs(K_MAIN, 128, k_main<Real, D, 128, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, MacroOut{},
-                  ObsOut{});
+        launch_bs(K_MAIN, 128, k_main<Real, D, 128, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, mo, ObsOut{});
         break;
       default:
-        launch_bs(K_MAIN, 256, k_main<Real, D, 256, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, MacroOut{},
-                  ObsOut{});
+        launch_bs(K_MAIN, 256, k_main<Real, D, 256, MODE_STEP, In, Out>, P_.N, P_, G_, R_, in, out, mo, ObsOut{});
     }
   }
 

@@ -349,6 +349,10 @@ struct MacroOut {
   double* kappa;
   double* force;  // [3][V]
   double* cvec;   // [3][V]
+  // MODE_STEP: when set, the node's force (xyz) and curvature (w) are also
+  // stored here (Vec4<Real>[Np], the layout of Grids::f), for a consumer that
+  // needs them after the step (the adjoint's kept front fields)
+  void* fstore;
 };
 
 // partial sums per block: [gridDim][kObsN]
@@ -424,6 +428,7 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
     f4.y = (Real)Fd[1];
     f4.z = (Real)Fd[2];
     f4.w = (Real)kd;
+    if (mo.fstore) static_cast<Vec4<Real>*>(mo.fstore)[n] = f4;
   } else {
     f4 = R.f[n];
   }
