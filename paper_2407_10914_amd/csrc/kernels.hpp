@@ -158,10 +158,12 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   const Pos ps = make_pos(P, v, fl & FL_FACE);
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
   Real ph[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
-    if constexpr (i > 0) ph[i] = R.phi[nb_vox<D, i>(P, ps)];
+    if constexpr (i > 0) ph[i] = R.phi[nbi[i]];
   });
   CT C[3] = {CT(0), CT(0), CT(0)};
   unroll<D>([&](auto A_) {
@@ -272,10 +274,12 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = Real;
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
   Vec4<Real> nb[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
-    if constexpr (i > 0) nb[i] = R.n[nb_vox<D, i>(P, ps)];
+    if constexpr (i > 0) nb[i] = R.n[nbi[i]];
   });
   CT d[3][3];
   unroll<D>([&](auto B_) {

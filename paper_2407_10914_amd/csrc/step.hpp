@@ -253,6 +253,26 @@ __device__ __forceinline__ int nb_vox(const StepParams& P, const Pos& p) {
   return p.face ? slow : fast;
 }
 
+// Neighbour voxels of p along every direction, idx[i] for i = 1..Q-1.  A wave
+// with no face node (almost all of them) takes a constant offset per direction
+// (a uniform branch); otherwise nb_vox's wrap/clamp path serves every lane.
+template <int D>
+__device__ __forceinline__ void nb_all(const StepParams& P, const Pos& p, int* idx) {
+  constexpr int Q = Lat<D>::Q;
+  if (__builtin_amdgcn_ballot_w64(p.face) == 0) {
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      constexpr int ex = Lat<D>::e(i, 0), ey = Lat<D>::e(i, 1), ez = Lat<D>::e(i, 2);
+      idx[i] = p.v + (ex + P.nx * (ey + P.ny * ez));
+    });
+  } else {
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      idx[i] = nb_vox<D, i>(P, p);
+    });
+  }
+}
+
 template <class Real, int D>
 __device__ __forceinline__ Real dotv(const Real* a, const Real* b) {
   Real s = a[0] * b[0];
