@@ -618,7 +618,7 @@ __device__ __forceinline__ void block_accumulate(const double* vals, int col0, d
 template <class Real, int D, bool kSeed, bool kMrt, class In>
 __global__ void __launch_bounds__(256) ka_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A,
                                                AdjParams AP) {
-  const int n = node_id();
+  const int n = node_id_plain();
   double lF[3] = {0.0, 0.0, 0.0};
   if (n < P.N) d_adj_node<Real, D, kSeed, kMrt, In>(P, G, R, in, A, AP, n, lF);
   block_accumulate<256, 3>(lF, 0, A.pacc);
@@ -729,7 +729,7 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
 // launch over both lists measured slower: 56 us against 28 + 17 us at 128^3).
 template <class Real, int D, bool kSb>
 __global__ void ka_curv(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A) {
-  d_adj_curv<Real, D, kSb>(P, G, R, A, node_id());
+  d_adj_curv<Real, D, kSb>(P, G, R, A, node_id_plain());
 }
 
 // ---------------------------------------------------------------- ka_normal
@@ -843,7 +843,7 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
 
 template <class Real, int D>
 __global__ void __launch_bounds__(256) ka_normal(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A, AdjParams AP) {
-  const int n = node_id();
+  const int n = node_id_plain();
   double lth = 0.0;
   if (n < P.N) d_adj_normal<Real, D>(P, G, R, A, AP, n, &lth);
   block_accumulate<256, 1>(&lth, 3, A.pacc);
@@ -900,7 +900,7 @@ __device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs
 
 template <class Real, int D>
 __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
-  const int s = node_id();
+  const int s = node_id_plain();
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
@@ -911,7 +911,7 @@ __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
 template <class Real, int D>
 __global__ void ka_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   constexpr int Q = Lat<D>::Q;
-  const int n = node_id();
+  const int n = node_id_plain();
   if (n >= P.N) return;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
@@ -941,7 +941,7 @@ __global__ void __launch_bounds__(BS) ka_obj(StepParams P, Geo<Real> G, Grids<Re
                                              double* part) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
-  const int n = node_id();
+  const int n = node_id_plain();
   double o[kObjN] = {0.0, 0.0, 0.0, 0.0};
   if (n < P.N) {
     const int v = vox_of(G.vf[n]);
@@ -1000,7 +1000,7 @@ template <class Real, int D, class In>
 __global__ void ka_seed_local(StepParams P, Geo<Real> G, In in, AdjParams AP, const double* sums, Real* lf,
                               Vec2<Real>* lr) {
   constexpr int Q = Lat<D>::Q;
-  const int n = node_id();
+  const int n = node_id_plain();
   if (n >= P.N) return;
   const int v = vox_of(G.vf[n]);
   const int c = coord_of(P, v, AP.axis);
@@ -1031,7 +1031,7 @@ __global__ void ka_seed_local(StepParams P, Geo<Real> G, In in, AdjParams AP, co
 template <class Real, int D>
 __global__ void ka_iden(StepParams P, Geo<Real> G, Real* iden) {
   constexpr int Q = Lat<D>::Q;
-  const int s = node_id();
+  const int s = node_id_plain();
   if (s >= P.nsb) return;
   const unsigned m = G.sb_mask[s];
   double den = 0.0;
@@ -1047,7 +1047,7 @@ __global__ void ka_iden(StepParams P, Geo<Real> G, Real* iden) {
 template <class Real, int D>
 __global__ void ka_idf(StepParams P, Geo<Real> G, double* idf) {
   constexpr int Q = Lat<D>::Q;
-  const int n = node_id();
+  const int n = node_id_plain();
   if (n >= P.N) return;
   double den = 0.0;
   unroll<Q - 1>([&](auto I) {
@@ -1062,7 +1062,7 @@ __global__ void ka_idf(StepParams P, Geo<Real> G, double* idf) {
 template <class Real, int D>
 __global__ void ka_theta_field(StepParams P, Geo<Real> G, const double* lth, double* out) {
   constexpr int Q = Lat<D>::Q;
-  const int s = node_id();
+  const int s = node_id_plain();
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];

@@ -214,7 +214,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
 
 template <class Real, int D>
 __global__ void k_normal(StepParams P, Geo<Real> G, Grids<Real> R) {
-  d_normal<Real, D>(P, G, R, node_id());
+  d_normal<Real, D>(P, G, R, node_id_plain());
 }
 
 // ------------------------------------------------------------------- k_sb_n

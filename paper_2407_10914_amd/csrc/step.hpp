@@ -182,9 +182,10 @@ struct Grids {
 
 // Block index -> logical tile, so that each of the 8 XCDs (blocks are dealt
 // round-robin) works on one contiguous range of nodes and keeps its stencil
-// neighbours in its own L2.  Used by the batched launch; the single-run
-// kernels keep the plain mapping, which measured the same or faster on the
-// 256^3 rock (k_normal 70 -> 62 us without the remap; the others within 1 %).
+// neighbours in its own L2.  With the plain mapping all XCDs work on the same
+// planes and k_main's L2 fetches grow from 1.0 to 1.68 GB per launch on the
+// 256^3 rock (the extra lines come from the other XCDs' working sets, which
+// the memory-side cache serves, so its time barely changes).
 __device__ __forceinline__ int xcd_tile(int bid, int nb) {
   const int per = nb >> 3, rem = nb & 7;
   const int x = bid & 7, k = bid >> 3;
@@ -192,6 +193,12 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 }
 
 __device__ __forceinline__ int node_id() {
+  return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+// Plain mapping, for k_normal (measured faster there: 70 -> 62 us on the
+// 256^3 rock; the other step kernels were within 1 % either way) and for the
+// adjoint kernels (reverse sweep 2.6 instead of 2.9 forward steps at 128^3).
+__device__ __forceinline__ int node_id_plain() {
   return blockIdx.x * blockDim.x + threadIdx.x;
 }
 
