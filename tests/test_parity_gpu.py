@@ -153,6 +153,26 @@ def test_fp32_per_step_drop_periodic():
     _fp32_step_parity(case, kw, 100, "drop")
 
 
+def test_fp32_per_step_full_size_rock_in_the_benchmark_configuration():
+    """The benchmark's own workload at full size: the 256^3 rock (4.6 M fluid
+    nodes, Type-I Zou-He, Scheme-I 30 deg, MRT), block sizes from the run's
+    tuner as bench.py uses them; after 60 steps the FP32 state, exported
+    exactly, goes into the oracle for one step (about 2 s on the host)."""
+    import bench
+
+    case, kw = bench.workload(256)
+    g = _sim(case, kw, "f32")
+    _say("rock256 tuning", g.tune(reps=3))
+    g.step(60)
+    fr, fb = g.populations()
+    o = O.OracleSim(case.solid, eps="f32", **kw)
+    o.set_state(fr, fb)
+    del fr, fb
+    g.step(1)
+    o.step(1)
+    _compare_macro(g, o, case.solid == 0, TOL32, "rock256 fp32 step 60->61")
+
+
 def test_fp32_mass_conservation_periodic_drop():
     """Per-colour mass over the whole relaxation of a drop (4000 steps: the
     interface moves for ~3000), where rounding biases of the recolouring
