@@ -60,3 +60,59 @@ def test_product_package_does_not_import_the_oracle():
                     assert all(not a.name.startswith("oracle") for a in node.names), f
                 if isinstance(node, ast.ImportFrom):
                     assert not (node.module or "").startswith("oracle"), f
+
+
+def _create(L, so, *, dim=3, shape=(6, 6, 6), tau=(1.0, 1.0), sigma=0.01, beta=0.7, scheme=1, theta=60.0,
+            bc=None, precision=None, collision=None):
+    import numpy as np
+
+    nz, ny, nx = shape
+    solid = np.zeros(shape, dtype=np.uint8)
+    geo = L.Geometry(dim, nx, ny, nz, solid.ctypes.data_as(ctypes.c_void_p), (ctypes.c_uint8 * 3)(1, 1, 1))
+    wet = L.Wetting(scheme, theta, None, 0)
+    opt = L.Options()
+    so.cg_options_default(ctypes.byref(opt), L.CG_FP32 if precision is None else precision)
+    if collision is not None:
+        opt.collision = collision
+    h = ctypes.c_void_p()
+    rc = so.cg_lbm_create(ctypes.byref(geo), tau[0], tau[1], sigma, beta, ctypes.byref(wet),
+                          None if bc is None else ctypes.byref(bc), ctypes.byref(opt), ctypes.byref(h))
+    return rc, so.cg_last_error()
+
+
+@pytest.mark.parametrize("case, code, words", [
+    (dict(tau=(0.5, 1.0)), "CG_EINVAL", b"tau"),
+    (dict(tau=(1.0, 0.3)), "CG_EINVAL", b"tau"),
+    (dict(beta=1.5), "CG_EINVAL", b"beta"),
+    (dict(sigma=float("nan")), "CG_EINVAL", b"sigma"),
+    (dict(scheme=3), "CG_EINVAL", b"scheme"),
+    (dict(theta=0.0), "CG_EINVAL", b"theta"),
+    (dict(theta=180.0), "CG_EINVAL", b"theta"),
+    (dict(dim=2, shape=(1, 6, 6), collision=1), "CG_EUNSUPPORTED", b"MRT"),
+    (dict(precision=7), "CG_EINVAL", b"precision"),
+])
+def test_create_rejects_invalid_parameters_before_any_device_call(case, code, words):
+    """Parameter checks of cg_lbm_create run before the device is touched, so
+    they hold on a machine without a GPU; each names what it rejects."""
+    from paper_2407_10914_amd import lib as L
+
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libcglbm.so not built")
+    so = L.load()
+    rc, msg = _create(L, so, **case)
+    assert rc == getattr(L, code), (rc, msg)
+    assert words in msg, msg
+
+
+def test_create_rejects_a_zou_he_face_in_2d_and_a_bad_colour_fraction():
+    from paper_2407_10914_amd import lib as L
+
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libcglbm.so not built")
+    so = L.load()
+    bc = L.BC(L.CG_BC_ZOUHE, 1.01, 1.0, 1.5, (ctypes.c_double * 3)(0.0, 0.0, 0.0))
+    rc, msg = _create(L, so, bc=bc)
+    assert rc == L.CG_EINVAL and b"zeta_r" in msg, msg
+    bc = L.BC(L.CG_BC_ZOUHE, 1.01, 1.0, 1.0, (ctypes.c_double * 3)(0.0, 0.0, 0.0))
+    rc, msg = _create(L, so, dim=2, shape=(1, 6, 6), collision=0, bc=bc)
+    assert rc == L.CG_EUNSUPPORTED and b"Zou-He" in msg, msg
