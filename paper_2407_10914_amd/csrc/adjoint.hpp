@@ -647,6 +647,8 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
     face = flags_of(vf) & FL_FACE;
   }
   const Pos ps = make_pos(P, v, face);
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
   CT acc[3] = {CT(0), CT(0), CT(0)};
   CT d[3][3] = {{CT(0), CT(0), CT(0)}, {CT(0), CT(0), CT(0)}, {CT(0), CT(0), CT(0)}};
   // a solid boundary point gathers from its fluid links only (lambda kappa is
@@ -662,7 +664,7 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
     constexpr double w = Lat<D>::w(j);
-    const int x = nb_vox<D, j>(P, ps);
+    const int x = nbi[j];
     Vec4<Real> q;
     CT lk;
     if constexpr (kSb) {
@@ -743,6 +745,8 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
   const Pos ps = make_pos(P, v, fl & FL_FACE);
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
   const double idf = A.idf[n];
   // lambda n: own part plus the transpose of Eq. (35) from the solid boundary
   // points next to a fluid boundary point
@@ -754,7 +758,7 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
     // lambda n, and adds an exact zero
     unroll<Q - 1>([&](auto J) {
       constexpr int j = J + 1;
-      const int x = nb_vox<D, j>(P, ps);
+      const int x = nbi[j];
       const Real id = A.iden[x];
       const Vec4<Real> q = A.ln[x];
       const CT c = (CT)Lat<D>::w(j) * (CT)id;
@@ -769,7 +773,7 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   CT C[3] = {CT(0), CT(0), CT(0)};
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
-    const CT ph = (CT)R.phi[nb_vox<D, j>(P, ps)];
+    const CT ph = (CT)R.phi[nbi[j]];
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
       constexpr int e = Lat<D>::e(j, a);
@@ -852,12 +856,12 @@ __global__ void __launch_bounds__(256) ka_normal(StepParams P, Geo<Real> G, Grid
 // ------------------------------------------------------- ka_sb_phi, ka_phi
 // C(x) = 3 sum_i w_i e_i phi(x + e_i)  =>  lambda phi(y) = -3 sum_j w_j e_j . lambda C(y + e_j)
 template <class Real, int D>
-__device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Real>& A, const Pos& ps) {
+__device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Real>& A, const int* nbi) {
   constexpr int Q = Lat<D>::Q;
   Real acc = Real(0);
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
-    const Vec4<Real> q = A.lc[nb_vox<D, j>(P, ps)];
+    const Vec4<Real> q = A.lc[nbi[j]];
     const Real qq[3] = {q.x, q.y, q.z};
     Real t = Real(0);
     unroll<D>([&](auto A_) {
@@ -875,7 +879,7 @@ __device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Re
 // written on fluid voxels alone (zero elsewhere), so the skipped terms are
 // exact zeros; masked buffer loads keep every gather in flight together.
 template <class Real, int D>
-__device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs<Real>& A, const Pos& ps,
+__device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs<Real>& A, const int* nbi,
                                               unsigned msk) {
   constexpr int Q = Lat<D>::Q;
   const auto rc = grid_rsrc(A.lc, sizeof(Vec4<Real>) * (size_t)P.V);
@@ -884,7 +888,7 @@ __device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs
     constexpr int j = J + 1;
     const bool on = msk & (1u << j);
     const Vec4<Real> q =
-        bload3<Real>(rc, on ? (uint32_t)nb_vox<D, j>(P, ps) * (uint32_t)sizeof(Vec4<Real>) : kOffNone);
+        bload3<Real>(rc, on ? (uint32_t)nbi[j] * (uint32_t)sizeof(Vec4<Real>) : kOffNone);
     const Real qq[3] = {q.x, q.y, q.z};
     Real t = Real(0);
     unroll<D>([&](auto A_) {
@@ -905,7 +909,9 @@ __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
-  A.lphi[v] = adj_grad_t_sb<Real, D>(P, A, ps, m) * A.iden[v];
+  int nbi[Lat<D>::Q];
+  nb_all<D>(P, ps, nbi);
+  A.lphi[v] = adj_grad_t_sb<Real, D>(P, A, nbi, m) * A.iden[v];
 }
 
 template <class Real, int D>
@@ -916,12 +922,14 @@ __global__ void ka_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
   const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
-  Real lp = adj_grad_t<Real, D>(P, A, ps);
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
+  Real lp = adj_grad_t<Real, D>(P, A, nbi);
   if (A.idf[n] != 0.0) {
     // transpose of Eq. (34): phi(s) = sum_i w_i phi(s + e_i) / sum_i w_i
     unroll<Q - 1>([&](auto J) {
       constexpr int j = J + 1;
-      lp = lp + (Real)Lat<D>::w(j) * A.lphi[nb_vox<D, j>(P, ps)];
+      lp = lp + (Real)Lat<D>::w(j) * A.lphi[nbi[j]];
     });
   }
   const Vec4<Real> na = A.na[n];

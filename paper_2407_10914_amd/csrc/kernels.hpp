@@ -121,12 +121,14 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
   const auto rs = grid_rsrc(R.phi, sizeof(Real) * (size_t)P.V);
   Real ph[Q];
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     const bool on = m & (1u << i);
-    const uint32_t off = on ? (uint32_t)nb_vox<D, i>(P, ps) * (uint32_t)sizeof(Real) : kOffNone;
+    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(Real) : kOffNone;
     ph[i] = bload1(rs, off, Real(0));
   });
   Real num = Real(0), den = Real(0);
@@ -227,12 +229,14 @@ __device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, 
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
+  int nbi[Q];
+  nb_all<D>(P, ps, nbi);
   const auto rs = grid_rsrc(R.n, sizeof(Vec4<Real>) * (size_t)P.V);
   Vec4<Real> q[Q];
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     const bool on = m & (1u << i);
-    const uint32_t off = on ? (uint32_t)nb_vox<D, i>(P, ps) * (uint32_t)sizeof(Vec4<Real>) : kOffNone;
+    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(Vec4<Real>) : kOffNone;
     q[i] = bload3<Real>(rs, off);
   });
   Real num[3] = {Real(0), Real(0), Real(0)};
