@@ -78,6 +78,9 @@ class Engine final : public EngineBase {
     int* nbr = narrow ? nullptr : (int*)dev(sizeof(int) * (Q - 1) * Np);
     int16_t* nbr16 = narrow ? (int16_t*)dev(sizeof(int16_t) * (Q - 1) * Np) : nullptr;
     int* nbase = narrow ? (int*)dev(sizeof(int) * (Q - 1) * (size_t)S.ntiles) : nullptr;
+    const bool tab8 = !S.nbr8.empty();
+    uint32_t* nbr8 = tab8 ? (uint32_t*)dev(sizeof(uint32_t) * S.nbr8.size()) : nullptr;
+    int* head8 = tab8 ? (int*)dev(sizeof(int) * S.nbr8_head.size()) : nullptr;
     unsigned* vf = (unsigned*)dev(sizeof(unsigned) * Np);
     const size_t nsb = S.sb_vox.size();
     int* sbv = (int*)dev(sizeof(int) * (nsb ? nsb : 1));
@@ -130,6 +133,10 @@ class Engine final : public EngineBase {
     } else {
       up(nbr, S.nbr.data(), sizeof(int) * (Q - 1) * Np);
     }
+    if (tab8) {
+      up(nbr8, S.nbr8.data(), sizeof(uint32_t) * S.nbr8.size());
+      up(head8, S.nbr8_head.data(), sizeof(int) * S.nbr8_head.size());
+    }
     up(vf, vfp.data(), sizeof(unsigned) * Np);
     up(sbv, S.sb_vox.data(), sizeof(int) * nsb);
     up(sbm, S.sb_mask.data(), sizeof(unsigned) * nsb);
@@ -144,7 +151,7 @@ class Engine final : public EngineBase {
       *err = std::string("upload failed: ") + hipGetErrorString(e);
       return CG_EHIP;
     }
-    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles, (int)Q - 1}, vf, sbv, sbm, nw, ct, stt};
+    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles, (int)Q - 1, nbr8, head8}, vf, sbv, sbm, nw, ct, stt};
     R_ = Grids<Real>{phi, ng, cv, fv};
     nsb_ = (int)nsb;
     dev_bytes_ = al_->total;

@@ -4,6 +4,7 @@
 #include "setup.hpp"
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <thread>
 
@@ -326,6 +327,68 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
     S.nbr16.clear();
     S.nbr_base.clear();
   }
+
+  // 8-bit pull table: per wave of 64 nodes and direction the smallest offset
+  // s - n of a fluid source, per node the remainder in 0..252 (253: the wave
+  // did not fit and reads the 16/32-bit table, 254 bounce-back, 255 open
+  // face).  Every entry of a fitting wave is decoded here and checked against
+  // the plain table; any mismatch drops the 8-bit table altogether.
+  {
+    const int qm1 = Q - 1, W8 = (qm1 + 3) / 4, nt64 = Np / 64;
+    S.nbr8.assign((size_t)nt64 * W8 * 64, 0xFDFDFDFDu);
+    S.nbr8_head.assign((size_t)nt64 * qm1, 0);
+    bool good = true;
+    long fitting = 0;
+    for (int t = 0; t < nt64 && good; ++t) {
+      const int n0 = t * 64, n1 = std::min(N, n0 + 64);
+      int* head = &S.nbr8_head[(size_t)t * qm1];
+      bool ok = true;
+      for (int i = 1; i < Q && ok; ++i) {
+        long lo = 0, hi = 0;
+        bool any = false;
+        for (int n = n0; n < n1; ++n) {
+          const int c = S.nbr[(size_t)(i - 1) * Np + n];
+          if (c < 0) continue;
+          const long d = (long)c - n;
+          lo = any ? std::min(lo, d) : d;
+          hi = any ? std::max(hi, d) : d;
+          any = true;
+        }
+        if (any && hi - lo > 252) ok = false;
+        head[i - 1] = (int)lo;
+      }
+      if (!ok) {
+        for (int i = 0; i < qm1; ++i) head[i] = 0;
+        continue;  // bytes stay 253: the whole wave takes the 16/32-bit table
+      }
+      ++fitting;
+      for (int i = 1; i < Q; ++i) {
+        for (int n = n0; n < n0 + 64; ++n) {
+          const int c = n < n1 ? S.nbr[(size_t)(i - 1) * Np + n] : kBounce;
+          const uint32_t byte = c >= 0 ? (uint32_t)((long)c - n - head[i - 1]) : (c == kOpen ? 255u : 254u);
+          uint32_t& w = S.nbr8[((size_t)t * W8 + (size_t)((i - 1) >> 2)) * 64 + (size_t)(n & 63)];
+          const int sh = 8 * ((i - 1) & 3);
+          w = (w & ~(0xFFu << sh)) | (byte << sh);
+        }
+      }
+      for (int i = 1; i < Q && good; ++i) {
+        for (int n = n0; n < n1; ++n) {
+          const uint32_t w = S.nbr8[((size_t)t * W8 + (size_t)((i - 1) >> 2)) * 64 + (size_t)(n & 63)];
+          const int byte = (int)((w >> (8 * ((i - 1) & 3))) & 0xFFu);
+          const long dec = byte < 253 ? (long)n + head[i - 1] + byte : (byte == 254 ? kBounce : (byte == 255 ? kOpen : -9));
+          if (dec != S.nbr[(size_t)(i - 1) * Np + n] || dec >= N) {
+            good = false;
+            break;
+          }
+        }
+      }
+    }
+    if (!good || fitting == 0) {
+      S.nbr8.clear();
+      S.nbr8_head.clear();
+    }
+  }
+
   return contact_angles(S, wet.theta_deg, field ? wet.theta_field_deg : nullptr, &S.cos_t, &S.sin_t, &S.flags,
                         err);
 }

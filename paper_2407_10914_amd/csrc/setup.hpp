@@ -25,6 +25,10 @@ struct HostSetup {
   std::vector<int16_t> nbr16;   // [(Q-1) * Np]
   std::vector<int> nbr_base;    // [(Q-1) * ntiles]
   int ntiles = 0;
+  // 8-bit pull table per wave of 64 nodes (see Nbr in step.hpp); empty when
+  // not used
+  std::vector<uint32_t> nbr8;   // [Np/64][(Q-1+3)/4][64]
+  std::vector<int> nbr8_head;   // [Np/64][Q-1]: the wave's base per direction
   std::vector<unsigned> flags;  // [Np]
   std::vector<int> sb_vox;      // [nsb]
   std::vector<unsigned> sb_mask;

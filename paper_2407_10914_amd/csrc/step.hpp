@@ -114,6 +114,13 @@ struct Nbr {
   const int* base;   // [Q-1][ntiles]
   const int* wide;   // [Q-1][Np] or nullptr
   int Np, ntiles, qm1;
+  // 8-bit table (on the 256^3 rock 99.8 % of the waves fit): per wave of 64
+  // nodes a base per direction, per node four directions to a 32-bit word,
+  // the byte being s - n - base_i, or 254 (bounce-back) / 255 (open face); a
+  // wave whose offsets do not fit holds 253 everywhere and reads the tables
+  // above instead, as does every single entry (get).  Null when not built.
+  const uint32_t* d8;  // [Np/64][(Q-1+3)/4][64]
+  const int* h8;       // [Np/64][Q-1]
   // One entry (any node, any lane).
   template <int i>
   __device__ __forceinline__ int get(int n) const {
@@ -129,6 +136,35 @@ struct Nbr {
   // once per wave, before any decode, and the decode is a select.
   template <int Q>
   __device__ __forceinline__ void all(int n, int* src) const {
+    if (d8) {
+      // words and bases are read unconditionally (no load waits on a flag),
+      // the decode is a select; a wave that holds the escape byte 253 (all of
+      // its bytes, set on the host) falls through to the 16/32-bit table
+      const int t = __builtin_amdgcn_readfirstlane(n >> 6);
+      constexpr int W8 = (Q - 1 + 3) / 4;
+      uint32_t w[W8];
+      unroll<W8>([&](auto K) {
+        constexpr int k = K;
+        w[k] = __builtin_nontemporal_load(&d8[(t * W8 + k) * 64 + (n & 63)]);
+      });
+      int b8[Q];
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        b8[i] = h8[t * (Q - 1) + (i - 1)];
+      });
+      bool esc = false;
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        const int byte = (int)((w[(i - 1) >> 2] >> (8 * ((i - 1) & 3))) & 0xFFu);
+        int s = n + b8[i] + byte;
+        // opaque: keeps the select from being turned into a branch with the
+        // base's load inside it
+        asm("" : "+v"(s));
+        src[i] = byte < 253 ? s : (byte == 254 ? kBounce : kOpen);
+        esc = esc || byte == 253;
+      });
+      if (__builtin_amdgcn_ballot_w64(esc) == 0) return;
+    }
     if (wide) {
       unroll<Q - 1>([&](auto I) {
         constexpr int i = I + 1;
