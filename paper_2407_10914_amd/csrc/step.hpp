@@ -238,27 +238,6 @@ __device__ __forceinline__ int node_id_plain() {
   return blockIdx.x * blockDim.x + threadIdx.x;
 }
 
-// Neighbour voxel of v along velocity (ex, ey, ez) for the gradient stencils:
-// periodic axes wrap, other axes clamp (zero-gradient ghosts beyond the open
-// faces; fluid nodes never reach past a wall face).
-__device__ __forceinline__ int nb_slow(const StepParams& P, int v, int ex, int ey, int ez) {
-  const int nxy = P.nx * P.ny;
-  int z = v / nxy;
-  int r = v - z * nxy;
-  int y = r / P.nx;
-  int x = r - y * P.nx;
-  x += ex;
-  y += ey;
-  z += ez;
-  if (x < 0) x = P.per[0] ? x + P.nx : 0;
-  if (x >= P.nx) x = P.per[0] ? x - P.nx : P.nx - 1;
-  if (y < 0) y = P.per[1] ? y + P.ny : 0;
-  if (y >= P.ny) y = P.per[1] ? y - P.ny : P.ny - 1;
-  if (z < 0) z = P.per[2] ? z + P.nz : 0;
-  if (z >= P.nz) z = P.per[2] ? z - P.nz : P.nz - 1;
-  return x + P.nx * (y + P.ny * z);
-}
-
 // A voxel and, when it lies on a domain face, its coordinates (decomposed once
 // per node rather than once per neighbour).
 struct Pos {
@@ -278,8 +257,11 @@ __device__ __forceinline__ Pos make_pos(const StepParams& P, int v, bool face) {
   return p;
 }
 
-// Branch-free: the wrapped/clamped index is formed for every node (from the
-// zero coordinates of an interior node it is simply unused) and selected.
+// Neighbour voxels for the gradient stencils: periodic axes wrap, other axes
+// clamp (zero-gradient ghosts beyond the open faces; fluid nodes never reach
+// past a wall face).  Branch-free: the wrapped/clamped index is formed for
+// every node (from the zero coordinates of an interior node it is simply
+// unused) and selected.
 __device__ __forceinline__ int wrap_or_clamp(int x, int n, bool per) {
   const int w = x + (x < 0 ? n : 0) - (x >= n ? n : 0);
   const int c = min(max(x, 0), n - 1);
