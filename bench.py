@@ -223,7 +223,7 @@ def main():
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the step runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 

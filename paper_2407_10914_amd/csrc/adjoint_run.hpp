@@ -1,4 +1,4 @@
-// Host driver of the discrete adjoint: forward sweep with checkpoints every K
+// Host side of the discrete adjoint: forward sweep with checkpoints every K
 // steps, then segment by segment (last first) the K states of the segment are
 // recomputed from its checkpoint into a ring of state buffers and the reverse
 // steps run from the last state of the segment down to its checkpoint.
