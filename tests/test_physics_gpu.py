@@ -1,8 +1,14 @@
-"""Physics read off the GPU path with the paper's own measurement: the
-sessile drop of Sec. III.B (the 64 x 32 D2Q9 case, input angle 60 deg through
-the surrounding fluid) relaxes to a cap whose angle, from its base and height
-(Eqs. 45-46), lies within the paper's +-4 deg band of 180 - 60 = 120 deg
-through the drop, in both precisions."""
+"""Physics read off the GPU path, with the paper's own measurements.
+
+The sessile drop of Sec. III.B (the 64 x 32 D2Q9 case, input angle 60 deg
+through the surrounding fluid) relaxes to a cap whose angle, from its base and
+height (Eqs. 45-46), lies within the paper's +-4 deg band of 180 - 60 = 120 deg
+through the drop, in both precisions.  Capillary filling of the C2 tube follows
+the linear limit of Washburn's law (viscosity ratio 1).  These runs are too
+long for the CPU oracle in a unit test (the C2 tube over 20000 steps is about
+half an hour on the host); the FP64 GPU path reproduces the oracle bit for bit
+on the same tube (test_parity_gpu.py), so the law pins the oracle's
+arithmetic as well."""
 import pytest
 
 from cases import c1_sessile_2d
@@ -24,3 +30,69 @@ def test_sessile_drop_contact_angle_from_base_and_height(precision):
     theta = M.cap_angle(b, h)
     print(f"{precision}: base {b:.3f} height {h:.3f} angle {theta:.2f} deg", flush=True)
     assert abs(theta - (180.0 - kw["theta_deg"])) < 4.0
+
+
+def _calibrated_tube(precision):
+    """Single-phase flux through the C2 tube under drho = 0.01 (all fluid b):
+    the effective radius r_eff of the staircase tube from Poiseuille's
+    Q = pi r^4 dP / (8 mu L) (dP = drho c_s^2, mu = nu at rho = 1)."""
+    import math
+
+    import numpy as np
+
+    from cases import c2_tube
+    from paper_2407_10914_amd.sim import Sim
+
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1")
+    nz = case.solid.shape[0]
+    g = Sim(case.solid, precision=precision, **kw)
+    g.set_phase(-np.ones(case.solid.shape))
+    g.step(20000)
+    Q = g.observe(axis=2, plane=nz // 2)["flux_t"]
+    dP = (kw["rho_in"] - kw["rho_out"]) / 3.0
+    mu = (kw["tau_b"] - 0.5) / 3.0
+    L = nz - 1
+    return Q, dP, (8.0 * mu * L * Q / (math.pi * dP)) ** 0.25
+
+
+@pytest.mark.parametrize("precision, scheme, drive, tol", [("f32", 1, "type1", 0.05), ("f64", 2, "type1", 0.05),
+                                                           ("f32", 1, "none", 0.09)])
+def test_washburn_front_speed_in_the_c2_tube(precision, scheme, drive, tol):
+    """Capillary filling of the C2 tube (Sec. IV.A; 24 x 24 x 400, theta = 45 deg
+    through the injected wetting fluid, viscosity ratio 1): with equal
+    viscosities the resistance does not depend on the front position, so the
+    front moves at the constant speed of the linear limit of Washburn's law,
+    dz/dt = (Q / A) (1 + 2 sigma cos(theta) / (r_eff dP)), Q and r_eff from the
+    single-phase calibration, A the 316-node cross-section.  Front from the
+    volume of the injected fluid, speed fitted over steps 5000-20000; within
+    5 % with the pressure drive (measured +1.3 %) and within the paper's own
+    Washburn errors of up to 9 % for pure capillary filling (the paper's
+    Case-I, drho = 0; measured +5.4 %: the whole drive is then the capillary
+    term, whose effective radius and dynamic angle the single-phase
+    calibration does not see)."""
+    import math
+
+    import numpy as np
+
+    from cases import c2_tube
+    from paper_2407_10914_amd.sim import Sim
+
+    Q, dP, reff = _calibrated_tube(precision)
+    case, kw = c2_tube(scheme=scheme, theta=45.0, drive=drive)
+    A = float((case.solid[200] == 0).sum())
+    pc = 2.0 * kw["sigma"] * math.cos(math.radians(kw["theta_deg"])) / reff
+    dP_run = (kw["rho_in"] - kw["rho_out"]) / 3.0
+    pred = Q / (A * dP) * (dP_run + pc)
+    g = Sim(case.solid, precision=precision, **kw)
+    g.set_phase(case.phi0)
+    ts, zs = [], []
+    for k in range(200):
+        g.step(100)
+        ts.append((k + 1) * 100)
+        zs.append(g.observe()["vol_b"] / A)
+    ts, zs = np.array(ts), np.array(zs)
+    m = ts >= 5000
+    slope = np.polyfit(ts[m], zs[m], 1)[0]
+    print(f"{precision} scheme {scheme} {drive}: r_eff {reff:.3f}, front speed {slope:.4e} "
+          f"against {pred:.4e} ({slope / pred - 1:+.2%})", flush=True)
+    assert abs(slope / pred - 1.0) < tol
