@@ -111,7 +111,12 @@ typedef void (*cg_free_fn)(void* ptr, void* ctx);
  * guards.  stream: a hipStream_t (NULL = the default stream).  alloc/free: an
  * optional device allocator (for example the PyTorch caching allocator); NULL
  * uses hipMalloc/hipFree.  block: threads per block for the node kernels
- * (0 = default). */
+ * (0 = default).  pull_table: the narrowest neighbour table the run may use,
+ * 0 or 8 = one byte per link and node with a base per wave of 64 nodes
+ * (default; waves whose offsets do not fit read the next table), 16 = two
+ * bytes per link with a base per tile of 256 nodes, 32 = one int32 node
+ * index per link; a narrower table is used only where its offsets fit, so
+ * results never depend on this choice (other values: CG_EINVAL). */
 typedef struct {
   int precision;
   int collision;
@@ -123,6 +128,7 @@ typedef struct {
   cg_free_fn free;
   void* alloc_ctx;
   int block;
+  int pull_table;
 } cg_options;
 
 /* Fill *opt with the defaults for the given precision: MRT, rho0 = 1,
@@ -208,6 +214,11 @@ typedef struct {
   int64_t voxels, fluid, fluid_boundary, solid_boundary, inlet, outlet;
   int64_t state_bytes;   /* bytes of one state copy on the device */
   int64_t device_bytes;  /* all device memory owned by the handle */
+  int pull_bits;         /* narrowest neighbour table built: 8, 16 or 32 */
+  int pull_fallback_bits;  /* the table that waves not fitting the 8-bit one
+                              read: 16 or 32 (0 when pull_bits is 16 or 32) */
+  int64_t pull_waves;      /* waves of 64 nodes */
+  int64_t pull_waves_8bit; /* waves that read the 8-bit table */
 } cg_info;
 
 cg_status cg_lbm_info(const cg_lbm* h, cg_info* out);

@@ -96,6 +96,8 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   if (geom->dim == 2 && o.collision == CG_MRT) return fail(CG_EUNSUPPORTED, "MRT is defined for D3Q19 only");
   if (geom->dim == 2 && b.type == CG_BC_ZOUHE) return fail(CG_EUNSUPPORTED, "Zou-He faces are defined for D3Q19");
   if (!(o.rho0 > 0.0)) return fail(CG_EINVAL, "rho0 must be positive");
+  if (o.pull_table != 0 && o.pull_table != 8 && o.pull_table != 16 && o.pull_table != 32)
+    return fail(CG_EINVAL, "pull_table must be 0, 8, 16 or 32");
   if (w.theta_field_deg) {
     const long V = (long)geom->nx * geom->ny * geom->nz;
     for (long v = 0; v < V; ++v)
@@ -113,7 +115,7 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   h->al.fr = o.free;
   h->al.ctx = o.alloc_ctx;
   std::string err;
-  int rc = cg::build_setup(*geom, w, b, &h->S, &err);
+  int rc = cg::build_setup(*geom, w, b, &h->S, &err, o.pull_table);
   if (rc != CG_OK) return fail((cg_status)rc, err);
   const cg::HostSetup& S = h->S;
   cg::StepParams& P = h->P;
@@ -290,6 +292,11 @@ cg_status cg_lbm_info(const cg_lbm* h, cg_info* out) {
   out->outlet = h->S.n_out;
   out->state_bytes = (int64_t)h->eng->state_bytes();
   out->device_bytes = (int64_t)h->eng->device_bytes();
+  const bool t16 = !h->S.nbr16.empty();
+  out->pull_bits = !h->S.nbr8.empty() ? 8 : (t16 ? 16 : 32);
+  out->pull_fallback_bits = out->pull_bits != 8 ? 0 : (t16 ? 16 : 32);
+  out->pull_waves = (int64_t)h->S.Np / 64;
+  out->pull_waves_8bit = (int64_t)h->S.n8_waves;
   return CG_OK;
 }
 

@@ -98,7 +98,8 @@ void smooth_pass(const Box& b, const std::vector<double>& g, std::vector<double>
 
 }  // namespace
 
-int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, HostSetup* out, std::string* err) {
+int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, HostSetup* out, std::string* err,
+                int pull_table) {
   HostSetup& S = *out;
   Box b;
   b.dim = g.dim;
@@ -292,7 +293,7 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
   S.ntiles = Np >> kTileShift;
   S.nbr16.assign((size_t)(Q - 1) * Np, (int16_t)kD16Bounce);
   S.nbr_base.assign((size_t)(Q - 1) * S.ntiles, 0);
-  bool fits = true;
+  bool fits = pull_table != 32;
   for (int i = 1; i < Q && fits; ++i) {
     for (int t = 0; t < S.ntiles && fits; ++t) {
       const int n0 = t << kTileShift, n1 = std::min(N, (t + 1) << kTileShift);
@@ -333,7 +334,7 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
   // did not fit and reads the 16/32-bit table, 254 bounce-back, 255 open
   // face).  Every entry of a fitting wave is decoded here and checked against
   // the plain table; any mismatch drops the 8-bit table altogether.
-  {
+  if (pull_table == 0 || pull_table == 8) {
     const int qm1 = Q - 1, W8 = (qm1 + 3) / 4, nt64 = Np / 64;
     S.nbr8.assign((size_t)nt64 * W8 * 64, 0xFDFDFDFDu);
     S.nbr8_head.assign((size_t)nt64 * qm1, 0);
@@ -386,7 +387,9 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
     if (!good || fitting == 0) {
       S.nbr8.clear();
       S.nbr8_head.clear();
+      fitting = 0;
     }
+    S.n8_waves = fitting;
   }
 
   return contact_angles(S, wet.theta_deg, field ? wet.theta_field_deg : nullptr, &S.cos_t, &S.sin_t, &S.flags,

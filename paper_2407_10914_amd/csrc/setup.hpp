@@ -29,6 +29,7 @@ struct HostSetup {
   // not used
   std::vector<uint32_t> nbr8;   // [Np/64][(Q-1+3)/4][64]
   std::vector<int> nbr8_head;   // [Np/64][Q-1]: the wave's base per direction
+  long n8_waves = 0;            // waves of the 8-bit table whose offsets fit
   std::vector<unsigned> flags;  // [Np]
   std::vector<int> sb_vox;      // [nsb]
   std::vector<unsigned> sb_mask;
@@ -49,7 +50,9 @@ struct HostSetup {
 int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
                    std::vector<double>* sin_t, std::vector<unsigned>* flags, std::string* err);
 
-// Returns CG_OK or an error with *err set.
-int build_setup(const cg_geometry& g, const cg_wetting& w, const cg_bc& bc, HostSetup* out, std::string* err);
+// pull_table: narrowest neighbour table to build (0 or 8, 16, 32; see
+// cg_options).  Returns CG_OK or an error with *err set.
+int build_setup(const cg_geometry& g, const cg_wetting& w, const cg_bc& bc, HostSetup* out, std::string* err,
+                int pull_table = 0);
 
 }  // namespace cg

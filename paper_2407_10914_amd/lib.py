@@ -61,7 +61,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("collision", C.c_int), ("rho0", C.c_double), ("eps_c", C.c_double),
                 ("eps_f", C.c_double), ("eps_v", C.c_double), ("device", C.c_int), ("stream", C.c_void_p),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p), ("block", C.c_int)]
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p), ("block", C.c_int),
+                ("pull_table", C.c_int)]
 
 
 class Observables(C.Structure):
@@ -76,7 +77,9 @@ class Observables(C.Structure):
 class Info(C.Structure):
     _fields_ = [(n, C.c_int) for n in ("dim", "q", "nx", "ny", "nz", "precision", "collision")] + \
                [(n, C.c_int64) for n in ("voxels", "fluid", "fluid_boundary", "solid_boundary", "inlet", "outlet",
-                                         "state_bytes", "device_bytes")]
+                                         "state_bytes", "device_bytes")] + \
+               [("pull_bits", C.c_int), ("pull_fallback_bits", C.c_int), ("pull_waves", C.c_int64),
+                ("pull_waves_8bit", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

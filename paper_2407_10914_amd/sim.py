@@ -48,7 +48,7 @@ class Sim:
     def __init__(self, solid, *, dim, periodic, tau_r=1.0, tau_b=1.0, sigma=0.0, beta=0.7, scheme=0,
                  theta_deg=90.0, theta_field=None, s1_line=0, bc=0, rho_in=1.0, rho_out=1.0, zeta_r=0.0,
                  g=(0.0, 0.0, 0.0), precision="f32", collision=None, rho0=1.0, eps_c=None, eps_f=None,
-                 eps_v=None, device=0, torch_alloc=True, block=0):
+                 eps_v=None, device=0, torch_alloc=True, block=0, pull_table=0):
         lib = L.load()
         solid = np.ascontiguousarray(solid, dtype=np.uint8)
         if solid.ndim == 2:
@@ -76,6 +76,7 @@ class Sim:
                 setattr(opt, k, v)
         opt.device = device
         opt.block = int(block)
+        opt.pull_table = int(pull_table)
         self._alloc = None
         if torch_alloc:
             self._alloc = TorchAllocator(device)

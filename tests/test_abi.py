@@ -116,3 +116,50 @@ def test_create_rejects_a_zou_he_face_in_2d_and_a_bad_colour_fraction():
     bc = L.BC(L.CG_BC_ZOUHE, 1.01, 1.0, 1.0, (ctypes.c_double * 3)(0.0, 0.0, 0.0))
     rc, msg = _create(L, so, dim=2, shape=(1, 6, 6), collision=0, bc=bc)
     assert rc == L.CG_EUNSUPPORTED and b"Zou-He" in msg, msg
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror of a header struct has the C size and the C offset
+    of each field (compiled with the host C compiler from include/cg_lbm.h)."""
+    import shutil
+    import subprocess
+
+    from paper_2407_10914_amd import lib as L
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"cg_geometry": L.Geometry, "cg_wetting": L.Wetting, "cg_bc": L.BC, "cg_options": L.Options,
+               "cg_observables": L.Observables, "cg_info": L.Info, "cg_adjoint_spec": L.AdjointSpec,
+               "cg_gradients": L.Gradients}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cg_lbm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c = {}
+    for ln in out:
+        if ln:
+            s, f, v = ln.split()
+            c[(s, f)] = int(v)
+    src_h = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "cg_lbm.h")).read(), flags=re.S)
+    for body, cname in re.findall(r"typedef struct\s*\{(.*?)\}\s*(cg_[a-z_]+)\s*;", src_h, flags=re.S):
+        if cname not in mirrors:
+            continue
+        declared = []
+        for decl in body.split(";"):
+            parts = [p.strip() for p in decl.split(",") if p.strip()]
+            for p in parts:
+                tok = re.sub(r"\[.*?\]", "", p).replace("*", " ").split()
+                declared.append(tok[-1])
+        assert declared == [f[0] for f in mirrors[cname]._fields_], cname
+    for cname, py in mirrors.items():
+        assert c[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert c[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
