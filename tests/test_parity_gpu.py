@@ -153,6 +153,32 @@ def test_fp32_per_step_drop_periodic():
     _fp32_step_parity(case, kw, 100, "drop")
 
 
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_fp32_per_step_d2q9_sessile_bgk(scheme):
+    """The two-dimensional compact state (D2Q9, BGK) on the C1 drop."""
+    case, kw = c1_sessile_2d()
+    kw = dict(kw, scheme=scheme)
+    _fp32_step_parity(case, kw, 300, f"C1 S-{scheme}")
+
+
+def test_fp32_per_step_d3q19_bgk_rock():
+    """Single-relaxation-time collision on the D3Q19 compact state."""
+    case, kw = rock(n=40, buffer=4)
+    kw = dict(kw, collision=0)
+    _fp32_step_parity(case, kw, 100, "rock40 BGK")
+
+
+def test_fp64_d3q19_bgk_short_tube_whole_run():
+    case, kw = c2_tube(scheme=2, theta=60.0, drive="type1", nz=40, wet_len=12)
+    kw = dict(kw, collision=0)
+    fluid = case.solid == 0
+    g = _sim(case, kw, "f64")
+    o = _orc(case, kw)
+    g.step(150)
+    o.step(150)
+    _compare_macro(g, o, fluid, TOL64, "C2 short BGK t=150")
+
+
 def test_fp32_per_step_full_size_rock_in_the_benchmark_configuration():
     """The benchmark's own workload at full size: the 256^3 rock (4.6 M fluid
     nodes, Type-I Zou-He, Scheme-I 30 deg, MRT), block sizes from the run's
