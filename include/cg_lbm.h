@@ -224,7 +224,13 @@ typedef struct {
 cg_status cg_lbm_info(const cg_lbm* h, cg_info* out);
 
 /* Opaque device-state snapshot (checkpoint / resume, bitwise).  dst/src are
- * host buffers of cg_info.state_bytes + 64 bytes. */
+ * caller-owned host buffers of cg_lbm_snapshot_bytes() bytes: a 64-byte header
+ * (time step, a fingerprint of precision, lattice, box and fluid node list)
+ * and the state.  Loading restores the state and the time step, not the
+ * parameters (angles, body force), and continues bit for bit as the run that
+ * saved it.  cg_lbm_load returns CG_EINVAL when the snapshot comes from a run
+ * of another geometry, lattice or precision.  Both calls synchronise the
+ * handle's stream. */
 int64_t cg_lbm_snapshot_bytes(const cg_lbm* h);
 cg_status cg_lbm_save(cg_lbm* h, void* dst);
 cg_status cg_lbm_load(cg_lbm* h, const void* src);

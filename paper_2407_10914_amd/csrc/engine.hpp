@@ -65,6 +65,26 @@ class Engine final : public EngineBase {
     Q_ = S.Q;
     const size_t Np = (size_t)S.Np, V = (size_t)S.V;
     const size_t Q = (size_t)S.Q;
+    // fingerprint of what a snapshot's bytes mean: precision, lattice,
+    // box and the fluid node list (FNV-1a, 64 bit)
+    {
+      uint64_t h = 1469598103934665603ull;
+      auto mix = [&](int64_t x) {
+        for (int k = 0; k < 8; ++k) {
+          h ^= (uint64_t)((x >> (8 * k)) & 0xff);
+          h *= 1099511628211ull;
+        }
+      };
+      mix((int64_t)sizeof(Real));
+      mix(S.dim);
+      mix(S.Q);
+      mix(S.nx);
+      mix(S.ny);
+      mix(S.nz);
+      mix(S.N);
+      for (int v : S.node_vox) mix(v);
+      fingerprint_ = (int64_t)h;
+    }
     bool alloc_failed = false;
     auto dev = [&](size_t bytes) -> void* {
       void* p = al_->get(bytes);
@@ -283,7 +303,7 @@ class Engine final : public EngineBase {
   int save(void* dst) override {
     CG_HIP(hipStreamSynchronize(stream_));
     char* p = (char*)dst;
-    int64_t hdr[8] = {t, pre_ ? 1 : 0, cur_, (int64_t)state_bytes_, (int64_t)pre_bytes(), 0, 0, 0};
+    int64_t hdr[8] = {t, pre_ ? 1 : 0, cur_, (int64_t)state_bytes_, (int64_t)pre_bytes(), fingerprint_, 0, 0};
     std::memcpy(p, hdr, 64);
     p += 64;
     for (auto& s : state_segments(cur_)) {
@@ -302,7 +322,10 @@ class Engine final : public EngineBase {
     const char* p = (const char*)src;
     int64_t hdr[8];
     std::memcpy(hdr, p, 64);
-    if (hdr[3] != (int64_t)state_bytes_ || hdr[4] != (int64_t)pre_bytes()) return CG_EINVAL;
+    if (hdr[3] != (int64_t)state_bytes_ || hdr[4] != (int64_t)pre_bytes() || hdr[5] != fingerprint_) {
+      err_ = "snapshot taken from a run of another geometry, lattice or precision";
+      return CG_EINVAL;
+    }
     p += 64;
     t = hdr[0];
     pre_ = hdr[1] != 0;
@@ -467,6 +490,7 @@ class Engine final : public EngineBase {
   double* obs_part_ = nullptr;
   double* obs_out_ = nullptr;
   size_t state_bytes_ = 0, dev_bytes_ = 0;
+  int64_t fingerprint_ = 0;
   std::vector<void*> owned_;
   // timing
   int timing_ = 0;
