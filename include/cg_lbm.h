@@ -337,6 +337,10 @@ void cg_batch_destroy(cg_batch* b);
 /* Enqueue n steps of every run (asynchronous). */
 cg_status cg_batch_step(cg_batch* b, int64_t n);
 cg_status cg_batch_sync(cg_batch* b);
+/* Observables of run i (0 <= i < n, the order given to cg_batch_create) after
+ * the batch's queued steps: waits for them, then does what cg_lbm_observe does
+ * on that run's handle (same axis/plane arguments and errors). */
+cg_status cg_batch_observe(cg_batch* b, int i, int axis, int plane, cg_observables* out);
 /* on = 0: enqueue the stage launches directly instead of replaying a graph. */
 cg_status cg_batch_set_graph(cg_batch* b, int on);
 /* Autotuner: for every stage, time each block size in {64, 128, 256} and

@@ -427,6 +427,14 @@ cg_status cg_batch_sync(cg_batch* b) {
   return rc == CG_OK ? CG_OK : fail((cg_status)rc, b->impl->err_);
 }
 
+cg_status cg_batch_observe(cg_batch* b, int i, int axis, int plane, cg_observables* out) {
+  if (!b) return fail(CG_EINVAL, "NULL batch");
+  if (i < 0 || i >= (int)b->runs.size()) return fail(CG_EINVAL, "run index out of range");
+  const cg_status rc = cg_batch_sync(b);
+  if (rc != CG_OK) return rc;
+  return cg_lbm_observe(b->runs[i], axis, plane, out);
+}
+
 cg_status cg_batch_set_graph(cg_batch* b, int on) {
   if (!b) return fail(CG_EINVAL, "NULL batch");
   b->impl->set_graph(on != 0);

@@ -28,7 +28,8 @@ EXPORTS = ("cg_options_default", "cg_lbm_create", "cg_lbm_destroy", "cg_last_err
            "cg_lbm_get_field", "cg_lbm_info", "cg_lbm_snapshot_bytes", "cg_lbm_save", "cg_lbm_load",
            "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing", "cg_batch_create",
            "cg_batch_destroy", "cg_batch_step", "cg_batch_sync", "cg_batch_set_graph", "cg_batch_tune",
-           "cg_batch_info", "cg_lbm_set_wetting", "cg_lbm_set_body_force", "cg_lbm_adjoint", "cg_lbm_tune")
+           "cg_batch_info", "cg_batch_observe", "cg_lbm_set_wetting", "cg_lbm_set_body_force", "cg_lbm_adjoint",
+           "cg_lbm_tune")
 
 OBJECTIVES = {"saturation": 0, "red_volume": 1, "flux": 2}
 
@@ -146,6 +147,7 @@ def load():
     L.cg_batch_destroy.restype = None
     L.cg_batch_step.argtypes = [p, i64]
     L.cg_batch_sync.argtypes = [p]
+    L.cg_batch_observe.argtypes = [p, i, i, i, C.POINTER(Observables)]
     L.cg_batch_set_graph.argtypes = [p, i]
     L.cg_batch_tune.argtypes = [p, i, C.c_char_p, C.c_size_t]
     L.cg_batch_info.argtypes = [p, C.POINTER(i64), p, p]

@@ -280,6 +280,12 @@ class Batch:
     def set_graph(self, on=True):
         L.check(L.load().cg_batch_set_graph(self._h, 1 if on else 0))
 
+    def observe(self, i, axis=-1, plane=0):
+        """Observables of run i after the queued steps (cg_batch_observe)."""
+        o = L.Observables()
+        L.check(L.load().cg_batch_observe(self._h, int(i), axis, plane, C.byref(o)))
+        return o.as_dict()
+
     def tune(self, reps=5):
         buf = C.create_string_buffer(4096)
         L.check(L.load().cg_batch_tune(self._h, int(reps), buf, 4096))

@@ -102,3 +102,25 @@ def test_run_stepped_alone_between_batch_steps():
         fluid = case.solid == 0
         for a, c in zip(_fields(s1), _fields(s2)):
             assert rel(c, a, fluid) == 0.0
+
+
+def test_batch_observe_reports_each_run():
+    """cg_batch_observe(i) after queued batch steps gives what the run's own
+    cg_lbm_observe gives, and what the run stepped alone gives (FP64: exactly)."""
+    from paper_2407_10914_amd.sim import Batch
+
+    specs = _specs()
+    solo = _runs("f64", specs)
+    batched = _runs("f64", specs)
+    b = Batch([s for _, s in batched])
+    b.step(7)
+    for _, s in solo:
+        s.step(7)
+    for k, ((case, s1), (_, s2)) in enumerate(zip(solo, batched)):
+        ob = b.observe(k)
+        assert ob == s2.observe()
+        o1 = s1.observe()
+        for key in ("step", "mass_r", "mass_b", "sat_nw_mass", "vol_r", "u_max"):
+            assert ob[key] == o1[key], (k, key, ob[key], o1[key])
+    with pytest.raises(Exception):
+        b.observe(len(specs))

@@ -120,3 +120,24 @@ def test_scheme1_literal_line_rule_fp64_against_the_oracle():
         r = rel(g.field(k), om[k], fluid)
         _say(k, f"{r:.3e}")
         assert r <= 1e-12, (k, r)
+
+
+def test_kernel_timing_counts_every_launch():
+    case, kw = rock(n=32, buffer=4)
+    s = _sim(case, kw, "f32")
+    s.set_timing("all")
+    s.step(5)
+    t = s.kernel_times()
+    _say(t)
+    for k in ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_main"):
+        assert t[k][0] == 5 and t[k][1] > 0.0, (k, t[k])
+    assert t["k_curv"][0] == 0
+    s.reset_timing()
+    assert all(c == 0 for c, _ in s.kernel_times().values())
+    s.set_timing(["k_main"])
+    s.step(2)
+    t = s.kernel_times()
+    assert t["k_main"][0] == 2 and t["k_phase"][0] == 0
+    s.set_timing(None)
+    s.step(1)
+    assert s.kernel_times()["k_main"][0] == 2
