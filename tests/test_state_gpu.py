@@ -1,11 +1,12 @@
-"""Checkpoint/resume and state import through the C ABI.
+"""Checkpoint/resume, state import and kernel timing through the C ABI.
 
 A run restored from a snapshot continues bit for bit as the run that saved
 it (both precisions, the snapshot carrying the time step); a snapshot does
 not load into a run of another geometry or precision; canonical populations
 exported from an FP64 run and imported into a fresh one (host or device
 buffers) continue bit for bit; the Scheme-I line option LITERAL agrees with
-the oracle as the default rule does.
+the oracle as the default rule does; the kernel timers count every launch of
+the kernels they are set for.
 """
 import sys
 
