@@ -4,7 +4,8 @@ The sessile drop of Sec. III.B (the 64 x 32 D2Q9 case, input angle 60 deg
 through the surrounding fluid) relaxes to a cap whose angle, from its base and
 height (Eqs. 45-46), lies within the paper's +-4 deg band of 180 - 60 = 120 deg
 through the drop, in both precisions.  Capillary filling of the C2 tube follows
-the linear limit of Washburn's law (viscosity ratio 1).  These runs are too
+the linear limit of Washburn's law (viscosity ratio 1).  A free 3D drop obeys
+the Laplace law and a body-force channel the Poiseuille parabola.  These runs are too
 long for the CPU oracle in a unit test (the C2 tube over 20000 steps is about
 half an hour on the host); the FP64 GPU path reproduces the oracle bit for bit
 on the same tube (test_parity_gpu.py), so the law pins the oracle's
@@ -96,3 +97,61 @@ def test_washburn_front_speed_in_the_c2_tube(precision, scheme, drive, tol):
     print(f"{precision} scheme {scheme} {drive}: r_eff {reff:.3f}, front speed {slope:.4e} "
           f"against {pred:.4e} ({slope / pred - 1:+.2%})", flush=True)
     assert abs(slope / pred - 1.0) < tol
+
+
+@pytest.mark.parametrize("precision, collision, tau_b, R, steps, tol", [
+    ("f32", "mrt", 0.6, 16.0, 16000, 0.01),
+    ("f32", "mrt", 1.0, 12.0, 6000, 0.02),
+    ("f64", "bgk", 1.0, 16.0, 6000, 0.01),
+])
+def test_laplace_law_for_a_free_3d_drop(precision, collision, tau_b, R, steps, tol):
+    """Delta p = 2 sigma / R for a free drop in 3D (the pressure of Eq. 23
+    inside and outside, R from the red volume) on a 64^3 periodic box: larger
+    drops than the oracle's own 28^3 pin can afford in a unit test.  With the
+    less viscous surrounding fluid (tau_b = 0.6) the pressure jump needs
+    about 16000 steps to settle (ratio 0.94 after 4000, 0.99 after 8000)."""
+    import numpy as np
+
+    from paper_2407_10914_amd import inputs
+    from paper_2407_10914_amd.sim import Sim
+
+    sigma = 0.01
+    c = inputs.drop_periodic((64, 64, 64), R)
+    g = Sim(c.solid, dim=3, periodic=c.periodic, tau_r=1.0, tau_b=tau_b, sigma=sigma, beta=0.95,
+            precision=precision, collision=collision)
+    g.set_phase(c.phi0)
+    g.step(steps)
+    o = g.observe()
+    r_eff = (3.0 * o["vol_r"] / (4.0 * np.pi)) ** (1.0 / 3.0)
+    dp = o["p_in"] - o["p_out"]
+    ratio = dp * r_eff / (2.0 * sigma)
+    print(f"{precision} {collision} tau_b={tau_b} R={R}: r_eff {r_eff:.3f} dp {dp:.4e} ratio {ratio:.4f}",
+          flush=True)
+    assert abs(ratio - 1.0) < tol
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_poiseuille_profile_in_a_3d_channel(precision):
+    """Body-force-driven channel between halfway bounce-back walls (D3Q19 MRT,
+    tau = 1): the steady profile is the parabola u = g/(2 nu) (y - 1/2)(ny - 3/2 - y)
+    with the walls half a node outside the fluid, to the precision of the run."""
+    import numpy as np
+
+    from paper_2407_10914_amd import inputs
+    from paper_2407_10914_amd.sim import Sim
+
+    ny, gx, tau = 18, 1e-5, 1.0
+    c = inputs.channel_3d(nx=4, ny=ny, nz=4)
+    g = Sim(c.solid, dim=3, periodic=c.periodic, tau_r=tau, tau_b=tau, g=(gx, 0.0, 0.0), precision=precision,
+            collision="mrt")
+    g.set_phase(c.phi0)
+    g.step(8000)
+    u = g.field("u")[0]
+    prof = u[1, :, 1]
+    nu = (tau - 0.5) / 3.0
+    y = np.arange(ny, dtype=float)
+    exact = gx / (2 * nu) * (y - 0.5) * (ny - 1.5 - y)
+    inner = slice(1, ny - 1)
+    err = np.abs(prof[inner] - exact[inner]).max() / exact.max()
+    print(f"{precision}: max relative deviation {err:.3e}", flush=True)
+    assert err < (1e-5 if precision == "f32" else 1e-9)
