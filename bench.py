@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--curve-steps", type=int, default=10000,
+                    help="after the timed region, continue the drainage to this step and record the saturation "
+                         "every tenth of it (0: off)")
     ap.add_argument("--no-tune", action="store_true", help="keep 256 threads per block for every kernel")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-k", type=int, default=100)
@@ -278,6 +281,20 @@ def main():
             "bytes_alg_per_launch": B_ALG_F32_D3Q19 * n_fluid, "avg_launch_us": round(main_avg_s * 1e6, 2),
             "block": main_block}
     step_frac = mlups * 1e6 * B_ALG_F32_D3Q19 / (HBM_PEAK_GBS * 1e9)
+    curve = None
+    if args.curve_steps > sim.time:
+        # the drainage itself, untimed: nonwetting saturation (mass based, all
+        # fluid nodes, buffers included) and the node-count wetting saturation
+        curve = []
+        every = max(1, args.curve_steps // 10)
+        while sim.time < args.curve_steps:
+            sim.step(min(every - sim.time % every, args.curve_steps - sim.time))
+            o = sim.observe(check=False)
+            curve.append([int(o["step"]), round(o["sat_nw_mass"], 6), round(o["sat_w"], 6)])
+            if o["nan_count"] > 0:
+                curve[-1].append("non-finite values in the state")
+                break
+        print(f"# saturation curve: {curve}", file=sys.stderr, flush=True)
     del sim
     torch.cuda.empty_cache()
     if args.copy_calib:
@@ -315,7 +332,10 @@ def main():
                                "porosity 0.22, Zou-He drho=0.02, Scheme-I 30 deg, MRT, FP32",
                    "fluid_nodes": n_fluid, "voxels": info["voxels"], "voxel_mlups": round(vox_mlups, 1),
                    "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3),
-                   "sat_nw_mass": obs["sat_nw_mass"], "tuning": tuning, "batched": batched, "adjoint": adj},
+                   "sat_nw_mass": obs["sat_nw_mass"], "tuning": tuning,
+                   "saturation_curve": None if curve is None else {"columns": ["step", "S_nw_mass", "S_w"],
+                                                                   "rows": curve},
+                   "batched": batched, "adjoint": adj},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
