@@ -1,0 +1,12 @@
+"""bench.py and its committed profiles agree (no GPU needed)."""
+
+
+def test_committed_traffic_profile_matches_the_step_kernel_sources():
+    """bench.py reports the HBM traffic of k_main from the committed rocprofv3
+    counter summary only while that summary was taken from the current step
+    kernel sources; this keeps the two in step (a kernel change needs a new
+    profile)."""
+    import bench
+
+    t = bench.read_traffic(4624221, 256)
+    assert t is not None and 1.2e9 < t < 1.6e9, t
