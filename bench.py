@@ -91,6 +91,39 @@ def cpu_baseline(case, kw, budget_s=20.0):
                        f"{el:.1f} s, OpenMP threads={threads}")
 
 
+def fp64_leg(case, kw, steps=50, warmup=5):
+    """The same 256^3 step in double precision (the build that reproduces the
+    oracle bit for bit): fluid-node MLUPS and k_main's algorithmic rate
+    (608 B per node), 256 threads per block."""
+    import torch
+
+    from paper_2407_10914_amd.sim import Sim
+
+    sim = Sim(case.solid, precision="f64", **kw)
+    sim.set_phase(case.phi0)
+    n_fluid = sim.info()["fluid"]
+    sim.step(warmup)
+    sim.sync()
+    sim.set_timing(["k_main"])
+    sim.reset_timing()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cnt, kms = sim.kernel_times()["k_main"]
+    sim.set_timing(None)
+    del sim
+    torch.cuda.empty_cache()
+    main_us = kms / max(cnt, 1) * 1e3
+    return {"mlups": round(n_fluid * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 4),
+            "k_main_us": round(main_us, 2),
+            "k_main_alg_gbs": round(2 * 19 * 2 * 8 * n_fluid / (main_us * 1e-6) / 1e9, 1), "steps": steps}
+
+
 def batched_leg(steps, warmup, count=64, ref_edge=256):
     """64 sessile-drop runs (edges drawn from {48, 64, 96, 128}, contact angles
     uniform in 15-165 deg, Scheme-I for even and Scheme-II for odd runs, FP32
@@ -216,6 +249,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision step of the same workload")
     ap.add_argument("--curve-steps", type=int, default=10000,
                     help="after the timed region, continue the drainage to this step and record the saturation "
                          "every tenth of it (0: off)")
@@ -305,6 +339,10 @@ def main():
         torch.cuda.synchronize()
         print("# copy calibration: 3 x 1 GiB device-to-device copies", file=sys.stderr, flush=True)
         del x, y
+    f64 = None
+    if not args.no_fp64:
+        f64 = fp64_leg(case, kw)
+        print(f"# fp64: {f64}", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batch:
         batched = batched_leg(args.batch_steps, max(2, args.warmup // 4))
@@ -335,7 +373,7 @@ def main():
                    "sat_nw_mass": obs["sat_nw_mass"], "tuning": tuning,
                    "saturation_curve": None if curve is None else {"columns": ["step", "S_nw_mass", "S_w"],
                                                                    "rows": curve},
-                   "batched": batched, "adjoint": adj},
+                   "fp64": f64, "batched": batched, "adjoint": adj},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
