@@ -94,3 +94,47 @@ def test_create_rejects_geometries_the_method_cannot_take(what, words):
         kw.update(periodic=(0, 0, 0), bc=1, rho_in=1.01, rho_out=1.0)
     with pytest.raises(CgError, match=words):
         Sim(solid, precision="f32", **kw)
+
+
+def _sphere_pack(n, period=32, radius=11):
+    x = np.arange(n, dtype=np.int32)
+    d = ((x % period) - period // 2) ** 2
+    return (d[:, None, None] + d[None, :, None] + d[None, None, :] < radius**2).astype(np.uint8)
+
+
+def test_largest_lattice_below_the_index_limit():
+    """512^3 voxels, 111.7 M fluid nodes (a periodic packing of spheres, FP32
+    MRT, Scheme-I, body force): fluid nodes times Q lies just below 2^31, the
+    16-byte normal grid spans 2^31 bytes, and the device holds about 54 GB.
+    The run keeps both colour masses to 1e-6 over 50 steps with a finite
+    state, reading a pull table that mixes 8-bit waves and fallback waves.
+    512^3 = 2^27 voxels is also the largest box (the per-node word holds a
+    27-bit voxel index): cg_lbm_create refuses 528^3, and 512^3 with smaller
+    spheres (more than 2^31 / 19 fluid nodes)."""
+    from paper_2407_10914_amd.sim import Sim
+
+    kw = dict(dim=3, periodic=(1, 1, 1), tau_r=1.0, tau_b=0.6, sigma=0.01, beta=0.95, scheme=1, theta_deg=60.0,
+              g=(0.0, 0.0, 1e-5), precision="f32", collision="mrt")
+    for geom, words in ((_sphere_pack(528, period=48, radius=10), "2^27 voxels"),
+                        (_sphere_pack(512, radius=8), "32-bit")):
+        with pytest.raises(Exception) as e:
+            Sim(geom, **kw)
+        print(str(e.value), flush=True)
+        assert words in str(e.value)
+    del geom
+    n = 512
+    solid = _sphere_pack(n)
+    x = np.arange(n)
+    phi = np.where((x[:, None, None] < 64) & (solid == 0), 1.0, -1.0)
+    s = Sim(solid, **kw)
+    inf = s.info()
+    print({k: inf[k] for k in ("fluid", "state_bytes", "device_bytes", "pull_waves", "pull_waves_8bit")}, flush=True)
+    assert inf["fluid"] * 19 < 2**31 and inf["fluid"] > 100_000_000
+    assert 0 < inf["pull_waves_8bit"] < inf["pull_waves"]
+    s.set_phase(phi)
+    a = s.observe()
+    s.step(50)
+    b = s.observe()
+    assert b["nan_count"] == 0
+    for k in ("mass_r", "mass_b"):
+        assert abs(b[k] / a[k] - 1.0) < 1e-6, (k, a[k], b[k])
