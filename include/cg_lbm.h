@@ -144,7 +144,9 @@ typedef struct cg_lbm cg_lbm;
  * three smoothing passes and the wall normal of Eqs. 25-26 in FP64, the
  * sparse fluid-node index and pull table), uploads it, and leaves the state
  * at rest with phi = -1 (all fluid b).  Errors: CG_EINVAL, CG_EUNSUPPORTED
- * (MRT or Zou-He with dim = 2), CG_ENOMEM, CG_EHIP.  *out receives the handle. */
+ * (MRT or Zou-He with dim = 2; more than 2^27 voxels; fluid nodes, rounded up
+ * to 256, times Q reaching 2^31; a 16-byte-per-voxel grid reaching 2^32
+ * bytes), CG_ENOMEM, CG_EHIP.  *out receives the handle. */
 cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, double sigma, double beta,
                         const cg_wetting* wet, const cg_bc* bc, const cg_options* opt, cg_lbm** out);
 
