@@ -3,8 +3,9 @@
 The sessile drop of Sec. III.B (the 64 x 32 D2Q9 case, input angle 60 deg
 through the surrounding fluid) relaxes to a cap whose angle, from its base and
 height (Eqs. 45-46), lies within the paper's +-4 deg band of 180 - 60 = 120 deg
-through the drop, in both precisions.  Capillary filling of the C2 tube follows
-the linear limit of Washburn's law (viscosity ratio 1).  A free 3D drop obeys
+through the drop, in both precisions, and the pressure jump across it is
+sigma / r (Laplace in 2D, measured 1.021).  Capillary filling of the C2 tube
+follows the linear limit of Washburn's law (viscosity ratio 1).  A free 3D drop obeys
 the Laplace law and a body-force channel the Poiseuille parabola.  These runs are too
 long for the CPU oracle in a unit test (the C2 tube over 20000 steps is about
 half an hour on the host); the FP64 GPU path reproduces the oracle bit for bit
@@ -29,8 +30,14 @@ def test_sessile_drop_contact_angle_from_base_and_height(precision):
     phi = g.field("phi")[0]
     b, h = M.drop_base_height(phi, wall=0.5)
     theta = M.cap_angle(b, h)
-    print(f"{precision}: base {b:.3f} height {h:.3f} angle {theta:.2f} deg", flush=True)
+    # the Laplace pressure jump across the cap (2D: sigma / r, r the radius of
+    # the circle through the base ends and the apex; pressures of Eq. 23)
+    o = g.observe()
+    r = (4.0 * h * h + b * b) / (8.0 * h)
+    lap = (o["p_in"] - o["p_out"]) * r / kw["sigma"]
+    print(f"{precision}: base {b:.3f} height {h:.3f} angle {theta:.2f} deg, dp r / sigma {lap:.4f}", flush=True)
     assert abs(theta - (180.0 - kw["theta_deg"])) < 4.0
+    assert abs(lap - 1.0) < 0.05
 
 
 def _calibrated_tube(precision):
