@@ -417,8 +417,13 @@ int contact_angles(const HostSetup& S, double theta_deg, const double* theta_fie
       }
       th = num / den;
     }
-    (*cos_t)[n] = std::cos(th * deg);
-    (*sin_t)[n] = std::sin(th * deg);
+    // one libm call for both (GNU sincos, the routine compilers also emit
+    // for a cos/sin pair of one argument; separate cos and sin calls can
+    // differ from it in the last place)
+    double sn, cs;
+    sincos(th * deg, &sn, &cs);
+    (*cos_t)[n] = cs;
+    (*sin_t)[n] = sn;
     unsigned& fl = (*flags)[n];
     fl &= ~FL_S1POS;
     if (S.s1_line == CG_S1_LITERAL || th > 90.0) fl |= FL_S1POS;
