@@ -85,6 +85,9 @@ def lib():
         L.orc_zouhe_outlet.argtypes = [p, p, d, d]
         L.orc_tangent.argtypes = [C.POINTER(Params), p, p, p, C.POINTER(TangentSpec), p, p]
         L.orc_objective.argtypes = [p, i, i, i, i, p]
+        L.orc_switch_inlet.argtypes = [p, d]
+        L.orc_set_pressure.argtypes = [p, d, d]
+        L.orc_set_body_force.argtypes = [p, p]
     return _LIB
 
 
@@ -278,6 +281,16 @@ class OracleSim:
         _check(lib().orc_tangent(C.byref(self.params), _ptr(self._solid), _ptr(self._theta_field),
                                  _ptr(_f64(phi0, self._solid.size)), C.byref(sp), C.byref(J), C.byref(dJ)))
         return J.value, dJ.value
+
+    def switch_inlet(self, zeta_r):
+        """Replace the injected fluid (Eqs. 37-38): 1.0 = red, 0.0 = blue."""
+        _check(lib().orc_switch_inlet(self._h, float(zeta_r)))
+
+    def set_pressure(self, rho_in, rho_out):
+        _check(lib().orc_set_pressure(self._h, float(rho_in), float(rho_out)))
+
+    def set_body_force(self, g):
+        _check(lib().orc_set_body_force(self._h, _ptr(_f64(g, 3))))
 
     def observe(self, axis=2, plane=0):
         o = Obs()

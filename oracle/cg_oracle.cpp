@@ -531,6 +531,7 @@ struct Sim {
     if (p.bc == 1 && (p.periodic[2] || nz < 3)) return fail("Zou-He needs a non-periodic z with nz >= 3");
     if (!(p.tau_r > 0.5) || !(p.tau_b > 0.5)) return fail("tau must exceed 1/2");
     if (p.beta < 0.0 || p.beta > 1.0) return fail("beta must lie in [0,1]");
+    if (p.scheme < 0 || p.scheme > 3) return fail("scheme must be 0, 1, 2 or 3");
     if (p.scheme != 0 && !(p.theta_deg > 0.0 && p.theta_deg < 180.0) && !theta_field)
       return fail("theta must lie in (0,180)");
     V = nx * ny * nz;
@@ -702,6 +703,42 @@ struct Sim {
     }
   }
 
+  /* Replacing the injected fluid in a restart, Eqs. (37)-(38) (Sec. II.D.1):
+   * at every inlet node the populations of the previously injected colour are
+   * added to those of the newly injected one and then cleared; later steps
+   * inject the new fluid (zeta^r = 1 for red, 0 for blue). */
+  int switch_inlet(double zeta_new) {
+    if (p.bc != 1) return fail("the injected fluid needs Zou-He faces");
+    if (zeta_new != 0.0 && zeta_new != 1.0) return fail("the new injected fluid must be pure (zeta_r 0 or 1)");
+    for (long y = 0; y < ny; ++y)
+      for (long x = 0; x < nx; ++x) {
+        const long v = idx(x, y, 0);
+        if (!fluid(v)) continue;
+        for (int i = 0; i < Q; ++i) {
+          R& a = fr[(size_t)i * V + v];
+          R& b = fb[(size_t)i * V + v];
+          if (zeta_new == 1.0) {
+            a = a + b; /* Eq. (37), s = r */
+            b = 0.0;   /* Eq. (38) */
+          } else {
+            b = b + a; /* Eq. (37), s = b */
+            a = 0.0;   /* Eq. (38) */
+          }
+        }
+      }
+    p.zeta_r = zeta_new;
+    return 0;
+  }
+
+  /* New Zou-He densities (Appendix B) for the next steps. */
+  int set_pressure(double rho_in, double rho_out) {
+    if (p.bc != 1) return fail("inlet/outlet densities need Zou-He faces");
+    if (!(rho_in > 0.0) || !(rho_out > 0.0)) return fail("densities must be positive");
+    p.rho_in = rho_in;
+    p.rho_out = rho_out;
+    return 0;
+  }
+
   /* Steps S1-S8 of one time step: densities and phase field, wetting
    * treatment, curvature, force, velocity.  Fills the macroscopic arrays. */
   void macro() {
@@ -729,9 +766,19 @@ struct Sim {
           if (fluid(vo)) phi[vo] = phi[idx(x, y, nz - 2)];
         }
     }
-    /* S2: phase field extrapolated to the solid boundary points, Eq. (34) */
+    /* S2: phase field extrapolated to the solid boundary points, Eq. (34);
+     * with the fictitious-density model the solid boundary points carry a
+     * fixed phase instead, Eq. (24).
+     * reading: Eq. (24) sets phi(x_s) = cos(theta) with theta measured through
+     * the red fluid; the angle here is measured through fluid b, as for the
+     * other schemes, so phi(x_s) = cos(180 deg - theta) = -cos(theta). */
     for (long s = 0; s < V; ++s) {
       if (!is_sb[s]) continue;
+      if (p.scheme == 3) {
+        const R th = has_field ? theta_vox_r[s] : theta_global;
+        phi[s] = -cos(th * (M_PI / 180.0));
+        continue;
+      }
       R num = 0.0;
       double den = 0.0;
       for (int i = 1; i < Q; ++i) {
@@ -758,7 +805,7 @@ struct Sim {
         for (int a = 0; a < D; ++a) n[a] = C[a] / cm;
       /* S4: wetting at the fluid boundary points (Sec. II.B, steps 2-3);
        * the norm |C| is kept and only the direction changes */
-      if (is_fb[v] && nw_ok[v] && cm > p.eps_c && p.scheme != 0) {
+      if (is_fb[v] && nw_ok[v] && cm > p.eps_c && (p.scheme == 1 || p.scheme == 2)) {
         double w3[3] = {nw[v], nw[V + v], nw[2 * V + v]};
         if (p.scheme == 1)
           scheme1(D, n, w3, cos_t[v], s1_sign[v], p.eps_f, p.eps_v);
@@ -1097,6 +1144,22 @@ int orc_stages(orc_sim* s, double* phi, double* n3, double* c3, double* kappa, d
       if (f3) f3[a * m.V + v] = f ? m.frc[a * m.V + v] : 0.0;
     }
   }
+  return 0;
+}
+
+int orc_switch_inlet(orc_sim* s, double zeta_r_new) {
+  if (!s) return fail("null argument");
+  return s->s.switch_inlet(zeta_r_new);
+}
+
+int orc_set_pressure(orc_sim* s, double rho_in, double rho_out) {
+  if (!s) return fail("null argument");
+  return s->s.set_pressure(rho_in, rho_out);
+}
+
+int orc_set_body_force(orc_sim* s, const double* g3) {
+  if (!s || !g3) return fail("null argument");
+  for (int a = 0; a < 3; ++a) s->s.gforce[a] = a < s->s.D ? g3[a] : 0.0;
   return 0;
 }
 

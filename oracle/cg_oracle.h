@@ -22,7 +22,7 @@ typedef struct {
   int nx, ny, nz;        /* nz = 1 for dim 2 */
   int periodic[3];       /* per axis */
   int collision;         /* 0 = BGK (Guo forcing), 1 = MRT (Sec. II.A) */
-  int scheme;            /* 0 = none, 1 = Scheme-I, 2 = Scheme-II (Sec. II.B) */
+  int scheme;            /* 0 = none, 1 = Scheme-I, 2 = Scheme-II (Sec. II.B), 3 = fictitious density (Eq. 24) */
   int s1_line;           /* Scheme-I secant start: 0 = sign rule, 1 = literal Eq. (30) */
   int bc;                /* 0 = closed/periodic, 1 = Zou-He inlet z=0 / outlet z=nz-1 */
   double tau_r, tau_b;   /* relaxation times of the two fluids, Eq. (13) */
@@ -68,6 +68,14 @@ int orc_macro(orc_sim* s, double* rho_r, double* rho_b, double* phi, double* u3)
 /* Stage dump of the current state: phi (fluid + S_b), n after wetting (fluid + S_b),
  * C after wetting, kappa, F; any pointer may be NULL. Vectors are [3][V]. */
 int orc_stages(orc_sim* s, double* phi, double* n3, double* c3, double* kappa, double* f3);
+/* Replace the injected fluid, Eqs. (37)-(38): at the inlet nodes the old
+ * colour's populations move to the new colour (zeta_r_new: 1 = red, 0 = blue),
+ * and later steps inject the new fluid.  Zou-He runs only. */
+int orc_switch_inlet(orc_sim* s, double zeta_r_new);
+/* New Zou-He inlet/outlet densities for the following steps. */
+int orc_set_pressure(orc_sim* s, double rho_in, double rho_out);
+/* New body-force acceleration g (Eq. 36) for the following steps. */
+int orc_set_body_force(orc_sim* s, const double* g3);
 /* axis: 0/1/2; plane: index on that axis */
 int orc_observe(orc_sim* s, int axis, int plane, orc_obs* out);
 /* cls: 0 interior solid, 1 S_b, 2 fluid, 3 F_b.  g3: smoothed image; nw3: [3][V];
