@@ -65,7 +65,14 @@ typedef struct {
   uint8_t periodic[3];
 } cg_geometry;
 
-enum { CG_WET_NONE = 0, CG_WET_SCHEME1 = 1, CG_WET_SCHEME2 = 2 };
+/* Wetting models (Sec. II.B): Scheme-I (Eqs. 28-31) and Scheme-II
+ * (Eqs. 32-33) change the interface normal at the fluid boundary points; the
+ * fictitious-density model (Eq. 24) instead fixes the phase of every solid
+ * boundary point to -cos(theta) (Eq. 24 written for an angle measured
+ * through fluid b: cos of the angle through fluid r) and leaves the normals
+ * as the colour gradient gives them.  The adjoint covers Scheme-I and
+ * Scheme-II only. */
+enum { CG_WET_NONE = 0, CG_WET_SCHEME1 = 1, CG_WET_SCHEME2 = 2, CG_WET_FICTITIOUS = 3 };
 /* Scheme-I secant start: SIGN_RULE takes v1 = n_c - (n_c + s n_w)/2 with
  * s = +1 for theta > 90 deg and s = -1 otherwise; LITERAL keeps s = +1 (Eq. 30
  * as printed). */
@@ -268,9 +275,73 @@ cg_status cg_lbm_tune(cg_lbm* h, int reps, char* report, size_t report_len);
  * holds this run sees the new angles (it references the run's arrays). */
 cg_status cg_lbm_set_wetting(cg_lbm* h, double theta_deg, const double* theta_field_deg);
 
-/* New body-force acceleration g (Eq. 36; force density rho_o g).  A batch
- * created earlier keeps the value it was created with. */
+/* New body-force acceleration g (Eq. 36; force density rho_o g) for the
+ * following steps.  Synchronises the stream.  A batch that holds this run
+ * picks up the new value at its next step. */
 cg_status cg_lbm_set_body_force(cg_lbm* h, const double g[3]);
+
+/* New Zou-He inlet and outlet densities (Appendix B, Eqs. B.1 and B.9) for
+ * the following steps, e.g. the pressure stages of a drainage or imbibition
+ * protocol (Sec. IV.B).  rho_in, rho_out > 0.  CG_EINVAL unless the run has
+ * CG_BC_ZOUHE faces.  Synchronises the stream; a batch that holds the run
+ * picks up the new values at its next step. */
+cg_status cg_lbm_set_pressure(cg_lbm* h, double rho_in, double rho_out);
+
+/* Replace the fluid injected at the inlet in a running simulation (Sec.
+ * II.D.1, Eqs. 37-38): at every inlet node the pre-collision populations of
+ * the previously injected colour are added to those of the new colour and
+ * then cleared, and the following steps inject the new fluid (zeta_r = 1:
+ * red, 0: blue; the inlet phase becomes +1 or -1).  The state is first
+ * written out as pre-collision populations at their own nodes (what the
+ * next step would pull), so the totals at every node are unchanged.
+ * CG_EINVAL unless the run has CG_BC_ZOUHE faces and zeta_r is 0 or 1.
+ * Synchronises the stream. */
+cg_status cg_lbm_switch_inlet(cg_lbm* h, double zeta_r);
+
+/* ---------------------------------------------------------------------- */
+/* Geometric observables of the phase field (on the device). */
+
+/* One grid line of the voxel box: the voxels with coordinate at[a] on every
+ * axis a != axis, and lo <= coordinate[axis] < hi.  blend in [0, 1): the
+ * profile is (1 - blend) phi(line) + blend phi(line shifted by one voxel
+ * along blend_axis), for a line that lies between two grid lines (blend = 0:
+ * the line itself; blend_axis is then ignored). */
+typedef struct {
+  int axis;
+  int at[3];
+  int lo, hi;
+  int blend_axis;
+  double blend;
+} cg_line;
+
+/* Interface points along a line: the positions (in voxel coordinates along
+ * the axis) where the linearly interpolated phase field of the current state
+ * (fluid nodes and solid boundary points) is zero, ascending.  points: host,
+ * max_points (<= 256) entries; *n_points receives the total count (more than
+ * max_points when there are more crossings; only max_points are written).
+ * The phase field is computed on the device and read along the line by one
+ * wavefront; nothing else crosses to the host.  CG_EINVAL for a line outside
+ * the box.  Synchronises the stream. */
+cg_status cg_lbm_line_crossings(cg_lbm* h, const cg_line* line, double* points, int max_points, int* n_points);
+
+/* Sessile drop on a flat wall (Sec. III.B, Eqs. 45-46), from the phase field
+ * in the plane spanned by base_axis and wall_axis (3D: at coordinate `slice`
+ * on the third axis).  The base b is the distance between the first and last
+ * interface points on the fluid row `row` next to the wall; the height h is
+ * the first interface point above `row` on the drop's axis (the base's
+ * midpoint, interpolated between the two nearest grid lines), measured from
+ * the wall position `wall` (0.5 for a halfway bounce-back wall whose first
+ * fluid row is 1).  radius = (4 h^2 + b^2) / (8 h) (Eq. 46); theta_deg =
+ * atan2(b/2, radius - h) in degrees (Eq. 45 extended past 90 degrees): the
+ * angle through the drop's own fluid.  CG_EINVAL when the row has fewer than
+ * two interface points or the axis none above the row.  Synchronises the
+ * stream. */
+typedef struct {
+  double base, height, radius, theta_deg;
+  int n_base_points;
+} cg_drop;
+
+cg_status cg_lbm_drop_shape(cg_lbm* h, int base_axis, int wall_axis, int slice, double wall, int row, cg_drop* out);
 
 /* ---------------------------------------------------------------------- */
 /* Discrete adjoint (reverse mode) of n_steps time steps from the current
@@ -357,6 +428,27 @@ cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len);
  * in step order: phase, sb_phi, normal, sb_n, main; grid 0 = one block per
  * tile) */
 cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid);
+/* Number of step graphs the batch has captured: one per starting ping-pong
+ * parity, so at most 2 until the configuration changes (cg_batch_tune,
+ * cg_batch_set_graph); -1 for a NULL batch. */
+int64_t cg_batch_graph_captures(const cg_batch* b);
+
+/* ---------------------------------------------------------------------- */
+/* Measurement: streaming reference kernels for the HBM roofline. */
+
+/* Time `reps` launches (after one untimed launch) of a plain streaming kernel
+ * over `bytes` bytes of device memory on `stream` (a hipStream_t, NULL = the
+ * default stream) and store the mean milliseconds per launch.  kind 0 reads
+ * src (dst: 16 writable bytes that are written only in a case that cannot
+ * occur), 1 writes dst, 2 copies src to dst.  The kernels move float4
+ * elements with a grid-stride loop of grid blocks of `block` threads (64 to
+ * 1024, a multiple of 64), four elements in flight per thread;
+ * nontemporal != 0 marks every access as streaming.  Bytes moved per launch:
+ * bytes (read, write) or 2 * bytes (copy).  src/dst: device pointers aligned
+ * to 16 bytes; bytes a multiple of 16.  Errors: CG_EINVAL, CG_EHIP.
+ * Synchronises the stream. */
+cg_status cg_stream_probe(int kind, const void* src, void* dst, size_t bytes, int grid, int block,
+                          int nontemporal, void* stream, int reps, float* ms_per_launch);
 
 #ifdef __cplusplus
 }

@@ -86,6 +86,7 @@ def lib():
         L.orc_tangent.argtypes = [C.POINTER(Params), p, p, p, C.POINTER(TangentSpec), p, p]
         L.orc_objective.argtypes = [p, i, i, i, i, p]
         L.orc_switch_inlet.argtypes = [p, d]
+        L.orc_set_threads.argtypes = [i]
         L.orc_set_pressure.argtypes = [p, d, d]
         L.orc_set_body_force.argtypes = [p, p]
     return _LIB
@@ -178,6 +179,11 @@ def zouhe_outlet(fr, fb, rho_out, phi_up):
     fr, fb = _f64(fr, 19).copy(), _f64(fb, 19).copy()
     lib().orc_zouhe_outlet(_ptr(fr), _ptr(fb), rho_out, phi_up)
     return fr, fb
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's node loops; returns the count in use."""
+    return lib().orc_set_threads(int(n))
 
 
 # ----------------------------------------------------------------- simulation

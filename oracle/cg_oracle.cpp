@@ -19,6 +19,9 @@
 
 #include <cmath>
 #include <cstdio>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1145,6 +1148,17 @@ int orc_stages(orc_sim* s, double* phi, double* n3, double* c3, double* kappa, d
     }
   }
   return 0;
+}
+
+/* OpenMP threads of the node loops (timing only: results do not depend on it). */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 int orc_switch_inlet(orc_sim* s, double zeta_r_new) {

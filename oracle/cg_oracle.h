@@ -72,6 +72,9 @@ int orc_stages(orc_sim* s, double* phi, double* n3, double* c3, double* kappa, d
  * colour's populations move to the new colour (zeta_r_new: 1 = red, 0 = blue),
  * and later steps inject the new fluid.  Zou-He runs only. */
 int orc_switch_inlet(orc_sim* s, double zeta_r_new);
+/* OpenMP threads of the node loops (n > 0 sets them); returns the count in use.
+ * Results do not depend on it: no loop reduces across nodes. */
+int orc_set_threads(int n);
 /* New Zou-He inlet/outlet densities for the following steps. */
 int orc_set_pressure(orc_sim* s, double rho_in, double rho_out);
 /* New body-force acceleration g (Eq. 36) for the following steps. */

@@ -24,6 +24,7 @@ SOURCES = [
     ("kernels_f32.hip", []),
     ("setup.cpp", ["-x", "hip", "-ffp-contract=off"]),
     ("capi.hip", []),
+    ("probe.hip", []),
 ]
 
 

@@ -786,7 +786,7 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   if (cm > (CT)P.eps_c) {
     CT ch[3] = {C[0] / cm, C[1] / cm, D == 3 ? C[2] / cm : CT(0)};
     CT lch[3], lcm = CT(0);
-    if ((fl & FL_WET) && P.scheme != 0) {
+    if ((fl & FL_WET) && (P.scheme == 1 || P.scheme == 2)) {
       TT nn[3], w3[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {

@@ -33,6 +33,10 @@ class AdjointRun {
       E.err_ = "the adjoint covers closed and periodic boundaries with the body force (no Zou-He faces)";
       return CG_EUNSUPPORTED;
     }
+    if (P.scheme == 3) {
+      E.err_ = "the adjoint covers Scheme-I and Scheme-II wetting (not the fictitious-density model)";
+      return CG_EUNSUPPORTED;
+    }
     if (sp.n_steps < 1 || sp.checkpoint_every < 1) {
       E.err_ = "n_steps and checkpoint_every must be >= 1";
       return CG_EINVAL;

@@ -7,7 +7,10 @@
 // table (the chunks are dealt so that each XCD gets contiguous work), and
 // each tile reads its run's parameters and array pointers from a descriptor
 // table in device memory.  Two descriptor tables (one per ping-pong parity)
-// let a two-step sequence be captured once in a hipGraph and replayed.
+// let a two-step sequence be captured once in a hipGraph and replayed; one
+// graph per starting parity, both captured once and kept while the tables'
+// addresses and the stage configuration stay the same (rewriting the tables'
+// contents does not invalidate them).
 // Block size and grid size per stage come from the autotuner below.
 #pragma once
 
@@ -85,8 +88,8 @@ class Batch final : public BatchBase {
  public:
   ~Batch() override {
     if (cap_stream_) (void)hipStreamSynchronize(cap_stream_);
-    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
-    if (graph_) (void)hipGraphDestroy(graph_);
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    drop_graphs();
     for (void* p : owned_) al_->put(p);
     if (ev_in_) (void)hipEventDestroy(ev_in_);
     if (ev_out_) (void)hipEventDestroy(ev_out_);
@@ -149,15 +152,20 @@ class Batch final : public BatchBase {
     return CG_OK;
   }
 
+  // A run stepped on its own, or given new parameters, since the tables were
+  // written: rewrite them.
+  int refresh() {
+    for (size_t r = 0; r < runs_.size(); ++r)
+      if (runs_[r]->t != t_expect_[r] || runs_[r]->params_version != v_expect_[r]) return upload_descs();
+    return CG_OK;
+  }
+
   int step(int64_t n) override {
     if (n <= 0) return CG_OK;
-    // a run stepped on its own since the tables were built: rebuild them
-    for (size_t r = 0; r < runs_.size(); ++r)
-      if (runs_[r]->t != t_expect_[r]) {
-        int rc = upload_descs();
-        if (rc != CG_OK) return rc;
-        break;
-      }
+    {
+      int rc = refresh();
+      if (rc != CG_OK) return rc;
+    }
     // runs holding a state set from the host take their first step on their own
     bool any_pre = false;
     for (Eng* r : runs_) any_pre = any_pre || r->pre();
@@ -174,29 +182,30 @@ class Batch final : public BatchBase {
       if (rc != CG_OK) return rc;
     }
     if (use_graph_ && n >= 2) {
-      if (!graph_exec_) {
-        int rc = capture();
+      if (!graph_exec_[par_]) {
+        int rc = capture(par_);
         if (rc != CG_OK) return rc;
       }
       if (hipEventRecord(ev_in_, stream_) != hipSuccess || hipStreamWaitEvent(cap_stream_, ev_in_, 0) != hipSuccess)
         return hip_fail("stream ordering");
+      // an even count of steps starts and ends on the same parity
       for (int64_t k = 0; k + 1 < n; k += 2) {
-        if (hipGraphLaunch(graph_exec_, cap_stream_) != hipSuccess) return hip_fail("hipGraphLaunch");
+        if (hipGraphLaunch(graph_exec_[par_], cap_stream_) != hipSuccess) return hip_fail("hipGraphLaunch");
       }
       if (hipEventRecord(ev_out_, cap_stream_) != hipSuccess || hipStreamWaitEvent(stream_, ev_out_, 0) != hipSuccess)
         return hip_fail("stream ordering");
       for (Eng* r : runs_) r->advance(n & ~int64_t(1));
       if (n & 1) {
-        enqueue_step(0);
+        enqueue_step(par_);
         for (Eng* r : runs_) r->advance(1);
-        swap_tables();
+        par_ ^= 1;
       }
     } else {
       for (int64_t k = 0; k < n; ++k) {
-        enqueue_step((int)(k & 1));
+        enqueue_step(par_);
+        par_ ^= 1;
       }
       for (Eng* r : runs_) r->advance(n);
-      if (n & 1) swap_tables();
     }
     for (size_t r = 0; r < runs_.size(); ++r) t_expect_[r] = runs_[r]->t;
     if (hipGetLastError() != hipSuccess) return hip_fail("batch launch");
@@ -210,8 +219,10 @@ class Batch final : public BatchBase {
 
   void set_graph(bool on) override {
     use_graph_ = on;
-    drop_graph();
+    drop_graphs();
   }
+
+  int64_t captures() const override { return captures_; }
 
   int64_t total_nodes() const override { return total_nodes_; }
 
@@ -223,20 +234,29 @@ class Batch final : public BatchBase {
     std::ostringstream os;
     const int bss[3] = {64, 128, 256};
     const int mults[5] = {0, 4, 8, 16, 32};
+    // the tables must describe the runs' current state: a run whose state
+    // was set from the host takes its first step (on its own) here
+    {
+      bool any_pre = false;
+      for (Eng* r : runs_) any_pre = any_pre || r->pre();
+      int rc = any_pre ? step(1) : refresh();
+      if (rc != CG_OK) return rc;
+    }
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hip_fail("event");
     // all stages depend on the previous ones only through data; timing one
-    // stage repeatedly on a valid state is safe (the main stage writes the
-    // other ping-pong buffer and does not change its own input)
+    // stage repeatedly on a valid state is safe (table par_ reads the
+    // current buffer; the main stage writes the other ping-pong buffer and
+    // does not change its own input)
     for (int st = 0; st < ST_COUNT; ++st) {
       double best = 1e30;
       StageCfg bc = cfg_[st];
       for (int bs : bss) {
         for (int m : mults) {
           StageCfg c{bs, m * cus_};
-          launch_stage(st, 0, c);  // warm-up
+          launch_stage(st, par_, c);  // warm-up
           (void)hipEventRecord(a, stream_);
-          for (int k = 0; k < reps; ++k) launch_stage(st, 0, c);
+          for (int k = 0; k < reps; ++k) launch_stage(st, par_, c);
           (void)hipEventRecord(b, stream_);
           if (hipEventSynchronize(b) != hipSuccess) {
             (void)hipEventDestroy(a);
@@ -258,7 +278,7 @@ class Batch final : public BatchBase {
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    drop_graph();
+    drop_graphs();
     save_tuning();
     if (report) *report = os.str();
     return CG_OK;
@@ -285,24 +305,35 @@ class Batch final : public BatchBase {
   bool use_graph_ = true;
   hipStream_t cap_stream_ = nullptr;
   hipEvent_t ev_in_ = nullptr, ev_out_ = nullptr;
-  hipGraph_t graph_ = nullptr;
-  hipGraphExec_t graph_exec_ = nullptr;
+  // graph p replays two steps starting from descriptor table p
+  hipGraph_t graph_[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec_[2] = {nullptr, nullptr};
+  int par_ = 0;  // descriptor table of the next step
+  int64_t captures_ = 0;
   int64_t total_nodes_ = 0;
   std::vector<int64_t> t_expect_;
+  std::vector<uint64_t> v_expect_;
 
   int hip_fail(const char* what) {
     err_ = std::string(what) + ": " + hipGetErrorString(hipGetLastError());
     return CG_EHIP;
   }
 
-  void drop_graph() {
-    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
-    if (graph_) (void)hipGraphDestroy(graph_);
-    graph_exec_ = nullptr;
-    graph_ = nullptr;
+  // Destroys both graphs once every replay queued on either stream is done.
+  void drop_graphs() {
+    if (!graph_exec_[0] && !graph_exec_[1]) return;
+    if (cap_stream_) (void)hipStreamSynchronize(cap_stream_);
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (int p = 0; p < 2; ++p) {
+      if (graph_exec_[p]) (void)hipGraphExecDestroy(graph_exec_[p]);
+      if (graph_[p]) (void)hipGraphDestroy(graph_[p]);
+      graph_exec_[p] = nullptr;
+      graph_[p] = nullptr;
+    }
   }
 
   // descriptor table q drives the step in which each run reads buffer cur ^ q
+  // (cur as it is when the tables are written; par_ restarts at 0)
   template <int D>
   int upload_descs_d() {
     std::vector<RunDesc<Real, D>> h(runs_.size());
@@ -320,16 +351,18 @@ class Batch final : public BatchBase {
     return CG_OK;
   }
   int upload_descs() {
-    drop_graph();
+    // queued launches (graph replays included) read the tables: let them
+    // finish before the contents change
+    if (cap_stream_ && hipStreamSynchronize(cap_stream_) != hipSuccess) return hip_fail("stream sync");
+    if (stream_ && hipStreamSynchronize(stream_) != hipSuccess) return hip_fail("stream sync");
     t_expect_.resize(runs_.size());
-    for (size_t r = 0; r < runs_.size(); ++r) t_expect_[r] = runs_[r]->t;
+    v_expect_.resize(runs_.size());
+    for (size_t r = 0; r < runs_.size(); ++r) {
+      t_expect_[r] = runs_[r]->t;
+      v_expect_[r] = runs_[r]->params_version;
+    }
+    par_ = 0;
     return dim_ == 3 ? upload_descs_d<3>() : upload_descs_d<2>();
-  }
-  // after an odd number of steps each run's current buffer flipped: the two
-  // tables exchange roles
-  void swap_tables() {
-    std::swap(descs_[0], descs_[1]);
-    drop_graph();
   }
 
   std::pair<int2*, int> tiles(bool sb, int bs) {
@@ -402,19 +435,19 @@ class Batch final : public BatchBase {
     for (int st = 0; st < ST_COUNT; ++st) launch_stage(st, q, cfg_[st], s);
   }
 
-  int capture() {
-    drop_graph();
+  int capture(int p) {
     // build every tile table first: capture must not allocate or copy
     for (int st = 0; st < ST_COUNT; ++st) tiles(stage_on_sb(st), cfg_[st].bs);
     if (hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return hip_fail("begin capture");
-    enqueue_step(0, cap_stream_);
-    enqueue_step(1, cap_stream_);
-    if (hipStreamEndCapture(cap_stream_, &graph_) != hipSuccess) return hip_fail("end capture");
-    if (hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0) != hipSuccess) {
-      graph_exec_ = nullptr;
+    enqueue_step(p, cap_stream_);
+    enqueue_step(p ^ 1, cap_stream_);
+    if (hipStreamEndCapture(cap_stream_, &graph_[p]) != hipSuccess) return hip_fail("end capture");
+    if (hipGraphInstantiate(&graph_exec_[p], graph_[p], nullptr, nullptr, 0) != hipSuccess) {
+      graph_exec_[p] = nullptr;
       return hip_fail("graph instantiate");
     }
+    ++captures_;
     return CG_OK;
   }
 

@@ -18,6 +18,8 @@ struct BatchBase {
   virtual int64_t total_nodes() const = 0;
   virtual int tune(int reps, std::string* report) = 0;
   virtual void get_config(int* bs, int* grid) const = 0;
+  // graphs captured so far (two at most while the configuration is unchanged)
+  virtual int64_t captures() const = 0;
   std::string err_;
 };
 

@@ -85,7 +85,7 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   if (!(tau_r > 0.5) || !(tau_b > 0.5)) return fail(CG_EINVAL, "tau_r and tau_b must exceed 1/2");
   if (!(beta >= 0.0 && beta <= 1.0)) return fail(CG_EINVAL, "beta must lie in [0, 1]");
   if (!std::isfinite(sigma)) return fail(CG_EINVAL, "sigma must be finite");
-  if (w.scheme < 0 || w.scheme > 2) return fail(CG_EINVAL, "unknown wetting scheme");
+  if (w.scheme < 0 || w.scheme > 3) return fail(CG_EINVAL, "unknown wetting scheme");
   if (w.scheme != 0 && !w.theta_field_deg && !(w.theta_deg > 0.0 && w.theta_deg < 180.0))
     return fail(CG_EINVAL, "theta must lie in (0, 180) degrees");
   if (b.type != CG_BC_NONE && b.type != CG_BC_ZOUHE) return fail(CG_EINVAL, "unknown boundary type");
@@ -144,6 +144,7 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   P.rho_in = b.rho_in;
   P.rho_out = b.rho_out;
   P.phi_in = b.zeta_r - (1.0 - b.zeta_r);
+  P.zeta_r = b.zeta_r;
   P.eps_c = o.eps_c;
   P.eps_f = o.eps_f;
   P.eps_v = o.eps_v;
@@ -324,16 +325,17 @@ cg_status cg_lbm_set_wetting(cg_lbm* h, double theta_deg, const double* theta_fi
   if (!h) return fail(CG_EINVAL, "NULL handle");
   if (!theta_field_deg && !(theta_deg > 0.0 && theta_deg < 180.0))
     return fail(CG_EINVAL, "theta must lie in (0, 180) degrees");
-  std::vector<double> ct = h->S.cos_t, st = h->S.sin_t;
+  std::vector<double> ct = h->S.cos_t, st = h->S.sin_t, fd = h->S.sb_fd;
   std::vector<unsigned> fl = h->S.flags;
   std::string err;
-  int rc = cg::contact_angles(h->S, theta_deg, theta_field_deg, &ct, &st, &fl, &err);
+  int rc = cg::contact_angles(h->S, theta_deg, theta_field_deg, &ct, &st, &fl, &fd, &err);
   if (rc != CG_OK) return fail((cg_status)rc, err);
-  rc = h->eng->set_angles(ct.data(), st.data(), fl.data());
+  rc = h->eng->set_angles(ct.data(), st.data(), fl.data(), fd.data());
   if (rc != CG_OK) return engine_status(h, rc);
   h->S.cos_t.swap(ct);
   h->S.sin_t.swap(st);
   h->S.flags.swap(fl);
+  h->S.sb_fd.swap(fd);
   return CG_OK;
 }
 
@@ -342,6 +344,101 @@ cg_status cg_lbm_set_body_force(cg_lbm* h, const double g[3]) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(g[a])) return fail(CG_EINVAL, "g must be finite");
   return engine_status(h, h->eng->set_body_force(g));
+}
+
+cg_status cg_lbm_set_pressure(cg_lbm* h, double rho_in, double rho_out) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  if (h->P.bc != CG_BC_ZOUHE) return fail(CG_EINVAL, "inlet/outlet densities need Zou-He faces");
+  if (!(rho_in > 0.0 && std::isfinite(rho_in)) || !(rho_out > 0.0 && std::isfinite(rho_out)))
+    return fail(CG_EINVAL, "densities must be positive and finite");
+  return engine_status(h, h->eng->set_pressure(rho_in, rho_out));
+}
+
+cg_status cg_lbm_switch_inlet(cg_lbm* h, double zeta_r) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  if (h->P.bc != CG_BC_ZOUHE) return fail(CG_EINVAL, "the injected fluid needs Zou-He faces");
+  if (zeta_r != 0.0 && zeta_r != 1.0) return fail(CG_EINVAL, "the new injected fluid must be pure (zeta_r 0 or 1)");
+  return engine_status(h, h->eng->switch_inlet(zeta_r));
+}
+
+cg_status cg_lbm_line_crossings(cg_lbm* h, const cg_line* line, double* points, int max_points, int* n_points) {
+  if (!h || !line || !n_points || (max_points > 0 && !points)) return fail(CG_EINVAL, "NULL argument");
+  if (max_points < 0 || max_points > cg::kLineMax) return fail(CG_EINVAL, "max_points must lie in [0, 256]");
+  const int dim = h->S.dim;
+  const int n[3] = {h->S.nx, h->S.ny, h->S.nz};
+  const int st[3] = {1, h->S.nx, h->S.nx * h->S.ny};
+  const int a = line->axis;
+  if (a < 0 || a >= dim) return fail(CG_EINVAL, "axis outside the lattice's dimensions");
+  if (!(line->lo >= 0 && line->lo < line->hi && line->hi <= n[a])) return fail(CG_EINVAL, "bad lo/hi");
+  int at[3] = {line->at[0], line->at[1], dim == 3 ? line->at[2] : 0};
+  at[a] = 0;
+  for (int k = 0; k < 3; ++k)
+    if (at[k] < 0 || at[k] >= n[k]) return fail(CG_EINVAL, "line outside the box");
+  int shift = 0;
+  const double t = line->blend;
+  if (!(t >= 0.0 && t < 1.0)) return fail(CG_EINVAL, "blend must lie in [0, 1)");
+  if (t > 0.0) {
+    const int b = line->blend_axis;
+    if (b < 0 || b >= dim || b == a) return fail(CG_EINVAL, "bad blend_axis");
+    if (at[b] + 1 >= n[b]) return fail(CG_EINVAL, "blended line outside the box");
+    shift = st[b];
+  }
+  const int v0 = at[0] + n[0] * (at[1] + n[1] * at[2]);
+  return engine_status(h, h->eng->line_crossings(v0, st[a], shift, t, line->lo, line->hi, max_points, points,
+                                                 n_points));
+}
+
+cg_status cg_lbm_drop_shape(cg_lbm* h, int base_axis, int wall_axis, int slice, double wall, int row, cg_drop* out) {
+  if (!h || !out) return fail(CG_EINVAL, "NULL argument");
+  const int dim = h->S.dim;
+  if (base_axis < 0 || base_axis >= dim || wall_axis < 0 || wall_axis >= dim || base_axis == wall_axis)
+    return fail(CG_EINVAL, "bad axes");
+  const int n[3] = {h->S.nx, h->S.ny, h->S.nz};
+  if (row < 0 || row >= n[wall_axis]) return fail(CG_EINVAL, "row outside the box");
+  std::memset(out, 0, sizeof(*out));
+  const int third = 3 - base_axis - wall_axis;
+  cg_line ln{};
+  ln.axis = base_axis;
+  ln.at[wall_axis] = row;
+  if (dim == 3) ln.at[third] = slice;
+  ln.lo = 0;
+  ln.hi = n[base_axis];
+  double xs[cg::kLineMax];
+  int nx = 0;
+  cg_status rc = cg_lbm_line_crossings(h, &ln, xs, cg::kLineMax, &nx);
+  if (rc != CG_OK) return rc;
+  out->n_base_points = nx;
+  if (nx < 2) return fail(CG_EINVAL, "fewer than two interface points on the row next to the wall");
+  const int last = (nx < cg::kLineMax ? nx : cg::kLineMax) - 1;
+  const double base = xs[last] - xs[0];
+  const double axis = 0.5 * (xs[0] + xs[last]);
+  const int x0 = (int)std::floor(axis);
+  cg_line up{};
+  up.axis = wall_axis;
+  up.at[base_axis] = x0;
+  if (dim == 3) up.at[third] = slice;
+  up.lo = row;
+  up.hi = n[wall_axis];
+  up.blend = axis - x0;
+  up.blend_axis = base_axis;
+  if (up.blend > 0.0 && x0 + 1 >= n[base_axis]) up.blend = 0.0;
+  double ys[cg::kLineMax];
+  int ny = 0;
+  rc = cg_lbm_line_crossings(h, &up, ys, cg::kLineMax, &ny);
+  if (rc != CG_OK) return rc;
+  double y = -1.0;
+  for (int k = 0; k < ny && k < cg::kLineMax; ++k)
+    if (ys[k] > row) {
+      y = ys[k];
+      break;
+    }
+  if (y < 0.0) return fail(CG_EINVAL, "no interface point above the wall on the drop axis");
+  const double hgt = y - wall;
+  out->base = base;
+  out->height = hgt;
+  out->radius = (4.0 * hgt * hgt + base * base) / (8.0 * hgt);
+  out->theta_deg = std::atan2(base / 2.0, out->radius - hgt) * (180.0 / M_PI);
+  return CG_OK;
 }
 
 cg_status cg_lbm_adjoint(cg_lbm* h, const cg_adjoint_spec* spec, cg_gradients* out) {
@@ -443,12 +540,6 @@ cg_status cg_batch_set_graph(cg_batch* b, int on) {
 
 cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len) {
   if (!b || reps < 1) return fail(CG_EINVAL, "bad argument");
-  bool any_pre = false;
-  for (cg_lbm* r : b->runs) any_pre = any_pre || cg_lbm_time(r) == 0;
-  if (any_pre) {
-    int rc = b->impl->step(1);
-    if (rc != CG_OK) return fail((cg_status)rc, b->impl->err_);
-  }
   std::string rep;
   int rc = b->impl->tune(reps, &rep);
   if (rc != CG_OK) return fail((cg_status)rc, b->impl->err_);
@@ -458,6 +549,8 @@ cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len) 
   }
   return CG_OK;
 }
+
+int64_t cg_batch_graph_captures(const cg_batch* b) { return b ? b->impl->captures() : -1; }
 
 cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid) {
   if (!b) return fail(CG_EINVAL, "NULL batch");

@@ -108,6 +108,7 @@ class Engine final : public EngineBase {
     Real* nw = (Real*)dev(sizeof(Real) * 3 * Np);
     Real* ct = (Real*)dev(sizeof(Real) * Np);
     Real* stt = (Real*)dev(sizeof(Real) * Np);
+    Real* sbfd = (Real*)dev(sizeof(Real) * (nsb ? nsb : 1));
     Real* phi = (Real*)dev(sizeof(Real) * V);
     V4* ng = (V4*)dev(sizeof(V4) * V);
     V4* cv = (V4*)dev(sizeof(V4) * Np);
@@ -115,6 +116,7 @@ class Engine final : public EngineBase {
     const int nb = (S.N + BS - 1) / BS;
     obs_part_ = (double*)dev(sizeof(double) * (size_t)kObsN * (nb + 1));
     obs_out_ = (double*)dev(sizeof(double) * kObsN);
+    line_buf_ = (double*)dev(sizeof(double) * (kLineMax + 1));
     if (kF32) {
       for (int k = 0; k < 2; ++k) {
         T_[k] = (float*)dev(sizeof(float) * Q * Np);
@@ -137,8 +139,9 @@ class Engine final : public EngineBase {
     // upload
     std::vector<unsigned> vfp(Np, 0u);
     for (int n = 0; n < S.N; ++n) vfp[n] = (unsigned)S.node_vox[n] | (S.flags[n] << kVoxBits);
-    std::vector<Real> nwr(3 * Np), ctr(Np), str(Np);
+    std::vector<Real> nwr(3 * Np), ctr(Np), str(Np), fdr(nsb);
     for (size_t i = 0; i < 3 * Np; ++i) nwr[i] = (Real)S.nw[i];
+    for (size_t i = 0; i < nsb; ++i) fdr[i] = (Real)S.sb_fd[i];
     for (size_t i = 0; i < Np; ++i) {
       ctr[i] = (Real)S.cos_t[i];
       str[i] = (Real)S.sin_t[i];
@@ -163,6 +166,7 @@ class Engine final : public EngineBase {
     up(nw, nwr.data(), sizeof(Real) * 3 * Np);
     up(ct, ctr.data(), sizeof(Real) * Np);
     up(stt, str.data(), sizeof(Real) * Np);
+    up(sbfd, fdr.data(), sizeof(Real) * nsb);
     if (e == hipSuccess) e = hipMemset(phi, 0, sizeof(Real) * V);
     if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(V4) * V);
     if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(V4) * Np);
@@ -171,7 +175,8 @@ class Engine final : public EngineBase {
       *err = std::string("upload failed: ") + hipGetErrorString(e);
       return CG_EHIP;
     }
-    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles, (int)Q - 1, nbr8, head8}, vf, sbv, sbm, nw, ct, stt};
+    G_ = Geo<Real>{Nbr{nbr16, nbase, nbr, (int)Np, S.ntiles, (int)Q - 1, nbr8, head8}, vf, sbv, sbm, nw, ct, stt,
+                   sbfd};
     R_ = Grids<Real>{phi, ng, cv, fv};
     nsb_ = (int)nsb;
     dev_bytes_ = al_->total;
@@ -275,6 +280,23 @@ class Engine final : public EngineBase {
     return CG_OK;
   }
 
+  int line_crossings(int v0, int stride, int shift, double t, int lo, int hi, int max_out, double* out,
+                     int* count) override {
+    if (dim_ == 3)
+      front<3>(2);
+    else
+      front<2>(2);
+    hipLaunchKernelGGL(k_line_crossings<Real>, dim3(1), dim3(64), 0, stream_, (const Real*)R_.phi, v0, stride, shift,
+                       t, lo, hi, max_out, line_buf_);
+    CG_HIP(hipGetLastError());
+    double h[kLineMax + 1];
+    CG_HIP(hipMemcpyAsync(h, line_buf_, sizeof(double) * (1 + max_out), hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    *count = (int)h[0];
+    for (int k = 0; k < max_out && k < *count; ++k) out[k] = h[1 + k];
+    return CG_OK;
+  }
+
   int export_pops(double* fr, double* fb) override {
     if (dim_ == 3)
       run_export<3>(fr, fb);
@@ -344,9 +366,10 @@ class Engine final : public EngineBase {
 
   int adjoint(const cg_adjoint_spec& sp, cg_gradients* g) override;
 
-  int set_angles(const double* cos_t, const double* sin_t, const unsigned* flags) override {
+  int set_angles(const double* cos_t, const double* sin_t, const unsigned* flags, const double* sb_fd) override {
     const size_t Np = P_.Np;
-    std::vector<Real> c(Np), s(Np);
+    std::vector<Real> c(Np), s(Np), fd(nsb_);
+    for (int k = 0; k < nsb_; ++k) fd[k] = (Real)sb_fd[k];
     std::vector<unsigned> vfp(Np);
     CG_HIP(hipStreamSynchronize(stream_));
     CG_HIP(hipMemcpy(vfp.data(), G_.vf, sizeof(unsigned) * Np, hipMemcpyDeviceToHost));
@@ -358,12 +381,51 @@ class Engine final : public EngineBase {
     CG_HIP(hipMemcpy(const_cast<Real*>(G_.cos_t), c.data(), sizeof(Real) * Np, hipMemcpyHostToDevice));
     CG_HIP(hipMemcpy(const_cast<Real*>(G_.sin_t), s.data(), sizeof(Real) * Np, hipMemcpyHostToDevice));
     CG_HIP(hipMemcpy(const_cast<unsigned*>(G_.vf), vfp.data(), sizeof(unsigned) * Np, hipMemcpyHostToDevice));
+    if (nsb_)
+      CG_HIP(hipMemcpy(const_cast<Real*>(G_.sb_fd), fd.data(), sizeof(Real) * nsb_, hipMemcpyHostToDevice));
+    ++params_version;
     return CG_OK;
   }
 
   int set_body_force(const double* g) override {
     CG_HIP(hipStreamSynchronize(stream_));
     for (int a = 0; a < 3; ++a) P_.rg[a] = a < dim_ ? P_.rho0 * g[a] : 0.0;
+    ++params_version;
+    return CG_OK;
+  }
+
+  // New Zou-He densities (Appendix B) for the following steps.
+  int set_pressure(double rho_in, double rho_out) override {
+    CG_HIP(hipStreamSynchronize(stream_));
+    P_.rho_in = rho_in;
+    P_.rho_out = rho_out;
+    P_.rin_r = rho_in * P_.zeta_r;
+    P_.rin_b = rho_in * (1.0 - P_.zeta_r);
+    ++params_version;
+    return CG_OK;
+  }
+
+  // Replace the injected fluid, Eqs. (37)-(38): the state is first written
+  // out as pre-collision populations at their own nodes (pull, bounce-back
+  // and faces applied, as the next step would see them), then at the inlet
+  // nodes the old colour's populations join the new colour's and are
+  // cleared; the following steps inject the new fluid.
+  int switch_inlet(double zeta_r) override {
+    if (dim_ == 3)
+      materialize<3>();
+    else
+      materialize<2>();
+    if (dim_ == 3)
+      launch(-1, k_switch_inlet<Real, 3>, P_.N, P_, G_, pre_r(), pre_x(), zeta_r == 1.0 ? 1 : 0);
+    else
+      launch(-1, k_switch_inlet<Real, 2>, P_.N, P_, G_, pre_r(), pre_x(), zeta_r == 1.0 ? 1 : 0);
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipStreamSynchronize(stream_));
+    P_.zeta_r = zeta_r;
+    P_.rin_r = P_.rho_in * zeta_r;
+    P_.rin_b = P_.rho_in * (1.0 - zeta_r);
+    P_.phi_in = zeta_r - (1.0 - zeta_r);
+    ++params_version;
     return CG_OK;
   }
 
@@ -489,6 +551,7 @@ class Engine final : public EngineBase {
   Real* pre_x_ = nullptr;
   double* obs_part_ = nullptr;
   double* obs_out_ = nullptr;
+  double* line_buf_ = nullptr;
   size_t state_bytes_ = 0, dev_bytes_ = 0;
   int64_t fingerprint_ = 0;
   std::vector<void*> owned_;
@@ -675,6 +738,23 @@ class Engine final : public EngineBase {
     launch(-1, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
     launch(-1, k_export<Real, D, In>, P_.N, P_, G_, R_, in, fr, fb);
   }
+  // Pre-collision populations of the current state at their own nodes
+  // (the staging that a state set from the host uses).  The double layout
+  // writes them into the other ping-pong buffer, which becomes current.
+  template <int D>
+  void materialize() {
+    if (pre_) return;
+    auto in = in_post<D>();
+    launch(-1, k_phase<Real, D, decltype(in)>, P_.N, P_, G_, R_, in);
+    if constexpr (kF32) {
+      launch(-1, k_materialize<Real, D, decltype(in)>, P_.N, P_, G_, R_, in, pre_r_, pre_x_);
+    } else {
+      launch(-1, k_materialize<Real, D, decltype(in)>, P_.N, P_, G_, R_, in, fr_[cur_ ^ 1], fb_[cur_ ^ 1]);
+      cur_ ^= 1;
+    }
+    pre_ = true;
+  }
+
   template <int D>
   void run_export(double* fr, double* fb) {
     if (pre_)

@@ -38,6 +38,9 @@ struct Alloc {
   }
 };
 
+// most interface points one line query returns
+constexpr int kLineMax = 256;
+
 enum { K_PHASE = 0, K_SB_PHI, K_NORMAL, K_SB_N, K_CURV, K_MAIN, K_COUNT };
 static const char* const kKernelNames[K_COUNT] = {"k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main"};
 
@@ -57,8 +60,14 @@ struct EngineBase {
   virtual int save(void* dst) = 0;
   virtual int load(const void* src) = 0;
   virtual int adjoint(const cg_adjoint_spec& sp, cg_gradients* g) = 0;
-  virtual int set_angles(const double* cos_t, const double* sin_t, const unsigned* flags) = 0;
+  virtual int set_angles(const double* cos_t, const double* sin_t, const unsigned* flags, const double* sb_fd) = 0;
   virtual int set_body_force(const double* g) = 0;
+  virtual int set_pressure(double rho_in, double rho_out) = 0;
+  // phi = 0 crossings along a line of the phase-field grid (see
+  // k_line_crossings); out receives min(count, max_out) positions
+  virtual int line_crossings(int v0, int stride, int shift, double t, int lo, int hi, int max_out, double* out,
+                             int* count) = 0;
+  virtual int switch_inlet(double zeta_r) = 0;
   virtual int tune(int reps, std::string* report) = 0;
   virtual void blocks(int* out) const = 0;
   virtual void set_timing(int mask) = 0;
@@ -67,6 +76,10 @@ struct EngineBase {
   virtual size_t state_bytes() const = 0;
   virtual size_t device_bytes() const = 0;
   int64_t t = 0;
+  // bumped whenever a parameter that the step kernels read changes (angles,
+  // body force, Zou-He densities, injected fluid): a batch holding the run
+  // re-reads its parameters then
+  uint64_t params_version = 0;
   std::string err_;
 };
 

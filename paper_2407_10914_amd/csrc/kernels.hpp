@@ -119,6 +119,11 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   constexpr int Q = Lat<D>::Q;
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
+  if (P.scheme == 3) {
+    // fictitious-density wetting: a fixed phase per solid boundary point
+    R.phi[v] = G.sb_fd[s];
+    return;
+  }
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
   int nbi[Q];
@@ -189,7 +194,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   if (cm > (CT)P.eps_c) {
 #pragma unroll
     for (int a = 0; a < D; ++a) nn[a] = C[a] / cm;
-    if ((fl & FL_WET) && P.scheme != 0) {
+    if ((fl & FL_WET) && (P.scheme == 1 || P.scheme == 2)) {
       CT w3[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) w3[a] = (CT)G.nw[a * P.Np + n];
@@ -648,6 +653,55 @@ __global__ void k_obs_final(const double* part, int nblocks, double* out) {
   if (threadIdx.x == 0) out[q] = sh[0];
 }
 
+// ------------------------------------------------------ interface points
+// Interface points along one grid line of the phase-field grid (Sec. III.B:
+// the drop's base and height are read where phi changes sign along a line;
+// Sec. IV.A: the front on the tube axis).  The profile is
+// p(k) = (1 - t) phi(v0 + k*stride) + t phi(v0 + shift + k*stride) for
+// k = lo .. hi-1 (t = 0: one line; otherwise blended with the parallel line
+// one voxel over, for an axis between two columns).  A crossing is k where
+// p(k) == 0, or k + p(k) / (p(k) - p(k+1)) where p(k) p(k+1) < 0, plus hi-1
+// when p(hi-1) == 0.  One wave scans the line in order and compacts the
+// crossings with ballots, so they come out ascending; at most max_out are
+// stored, out[0] receives their total count.  Evaluated without fused
+// multiply-adds (the same roundings as the plain expression in double).
+template <class Real>
+__global__ void __launch_bounds__(64) k_line_crossings(const Real* phi, int v0, int stride, int shift, double t,
+                                                       int lo, int hi, int max_out, double* out) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x;
+  int found = 0;
+  for (int base = lo; base < hi; base += 64) {
+    const int k = base + lane;
+    double pos = 0.0;
+    bool hit = false;
+    if (k < hi) {
+      auto prof = [&](int kk) {
+        const double a = (double)phi[v0 + kk * stride];
+        if (t == 0.0) return a;
+        const double b = (double)phi[v0 + shift + kk * stride];
+        return (1.0 - t) * a + t * b;
+      };
+      const double a = prof(k);
+      if (a == 0.0) {
+        hit = true;
+        pos = (double)k;
+      } else if (k + 1 < hi) {
+        const double b = prof(k + 1);
+        if (a * b < 0.0) {
+          hit = true;
+          pos = (double)k + ((double)(k + 1) - (double)k) * a / (a - b);
+        }
+      }
+    }
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(hit);
+    const int before = __builtin_popcountll(m & ((1ull << lane) - 1ull));
+    if (hit && found + before < max_out) out[1 + found + before] = pos;
+    found += __builtin_popcountll(m);
+  }
+  if (lane == 0) out[0] = (double)found;
+}
+
 // -------------------------------------------------------- state transfer
 // Canonical pre-collision populations of the current state, as FP64 dense
 // [Q][V] arrays (pull, bounce-back and faces applied; the compact layout is
@@ -671,6 +725,55 @@ __global__ void k_export(StepParams P, Geo<Real> G, Grids<Real> R, In in, double
     fr_out[(size_t)i * P.V + v] = fr[i];
     fb_out[(size_t)i * P.V + v] = kDev ? ((Lat<D>::w(i) * P.rho0 + fx[i]) - fr[i]) : fx[i];
   }
+}
+
+// Pre-collision populations of the current state at their own nodes (pull,
+// bounce-back and faces applied, as d_main sees them), in the staging layout
+// of a state set from the host: (f^r, f^b) for double, (f^r, g) for float.
+template <class Real, int D, class In>
+__global__ void k_materialize(StepParams P, Geo<Real> G, Grids<Real> R, In in, Real* r_out, Real* x_out) {
+  constexpr int Q = Lat<D>::Q;
+  constexpr bool kDev = sizeof(Real) == 4;
+  const int n = node_id();
+  if (n >= P.N) return;
+  const unsigned vf = ld_once(&G.vf[n]);
+  const int v = vox_of(vf);
+  const unsigned fl = flags_of(vf);
+  Real fr[Q], fx[Q];
+  load_node<D>(in, G.nbr, n, fr, fx);
+  if constexpr (In::kPull) {
+    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    r_out[i * P.Np + n] = fr[i];
+    x_out[i * P.Np + n] = fx[i];
+  }
+}
+
+// Eqs. (37)-(38) on the staged pre-collision populations of the inlet nodes:
+// the previously injected colour joins the newly injected one (to_red: red)
+// and is cleared.  Float staging holds (f^r, g = f^t - w rho0): only f^r
+// changes, to the total or to zero.
+template <class Real, int D>
+__global__ void k_switch_inlet(StepParams P, Geo<Real> G, Real* r, Real* x, int to_red) {
+  constexpr int Q = Lat<D>::Q;
+  constexpr bool kDev = sizeof(Real) == 4;
+  const int n = node_id();
+  if (n >= P.N) return;
+  if (!(flags_of(G.vf[n]) & FL_IN)) return;
+  unroll<Q>([&](auto I) {
+    constexpr int i = I;
+    const int k = i * P.Np + n;
+    if constexpr (kDev) {
+      const Real tot = (Real)Lat<D>::w(i) * (Real)P.rho0 + x[k];
+      r[k] = to_red ? tot : Real(0);
+    } else {
+      const Real a = r[k], b = x[k];
+      r[k] = to_red ? a + b : Real(0);
+      x[k] = to_red ? Real(0) : b + a;
+    }
+  });
 }
 
 // Dense FP64 canonical populations -> pre-collision staging at the nodes.

@@ -392,13 +392,21 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
     S.n8_waves = fitting;
   }
 
+  S.sb_fd.assign(S.sb_vox.size(), 0.0);
   return contact_angles(S, wet.theta_deg, field ? wet.theta_field_deg : nullptr, &S.cos_t, &S.sin_t, &S.flags,
-                        err);
+                        &S.sb_fd, err);
 }
 
 int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
-                   std::vector<double>* sin_t, std::vector<unsigned>* flags, std::string* err) {
+                   std::vector<double>* sin_t, std::vector<unsigned>* flags, std::vector<double>* sb_fd,
+                   std::string* err) {
   const double deg = M_PI / 180.0;
+  // Eq. (24) with the angle measured through fluid b: the fixed phase of a
+  // solid boundary point is cos(180 deg - theta) = -cos(theta)
+  for (size_t k = 0; k < S.sb_vox.size(); ++k) {
+    const double th = theta_field_deg ? theta_field_deg[S.sb_vox[k]] : theta_deg;
+    (*sb_fd)[k] = -std::cos(th * deg);
+  }
   for (size_t k = 0; k < S.fb_node.size(); ++k) {
     const int n = S.fb_node[k];
     double th;

@@ -35,6 +35,7 @@ struct HostSetup {
   std::vector<unsigned> sb_mask;
   std::vector<double> nw;       // [3 * Np]
   std::vector<double> cos_t, sin_t;  // [Np]
+  std::vector<double> sb_fd;    // [nsb] fictitious-density phase -cos(theta), Eq. (24)
   std::vector<double> g3;       // smoothed image [V] (kept for diagnostics)
   // solid link neighbours of each fluid boundary point, i ascending:
   // fb_node[k] has links fb_off[k] .. fb_off[k+1]-1 to voxels fb_vox with weights fb_w
@@ -45,10 +46,12 @@ struct HostSetup {
 
 // Contact angle at every fluid boundary point from the global angle or the
 // per-voxel field (w_i-weighted mean over the solid link neighbours): fills
-// cos_t, sin_t and the FL_S1POS bit of flags for those nodes ([Np] each).
-// Returns CG_OK or CG_EINVAL with *err set.
+// cos_t, sin_t and the FL_S1POS bit of flags for those nodes ([Np] each),
+// and the fictitious-density phase of every solid boundary point from its
+// own angle (sb_fd, [nsb]).  Returns CG_OK or CG_EINVAL with *err set.
 int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
-                   std::vector<double>* sin_t, std::vector<unsigned>* flags, std::string* err);
+                   std::vector<double>* sin_t, std::vector<unsigned>* flags, std::vector<double>* sb_fd,
+                   std::string* err);
 
 // pull_table: narrowest neighbour table to build (0 or 8, 16, 32; see
 // cg_options).  Returns CG_OK or an error with *err set.

@@ -61,7 +61,7 @@ struct StepParams {
   int V;     // voxels
   int per[3];
   int bc;    // 0 none, 1 Zou-He z faces
-  int scheme;
+  int scheme;     // 0 none, 1 Scheme-I, 2 Scheme-II, 3 fictitious density (Eq. 24)
   int collision;  // 0 BGK, 1 MRT
   double half_sigma;  // 0.5 * sigma
   double beta, rho0;
@@ -69,7 +69,7 @@ struct StepParams {
   float hinv_nu_r, hinv_nu_b;  // 1/(2 nu_r), 1/(2 nu_b) for the single-precision rates
   double rg[3];       // rho0 * g, force density of Eq. (36)
   double rin_r, rin_b;  // rho_in * zeta^r, rho_in * zeta^b
-  double rho_in, rho_out, phi_in;
+  double rho_in, rho_out, phi_in, zeta_r;
   double eps_c, eps_f, eps_v;
   int flux_axis, flux_plane;
 };
@@ -204,6 +204,7 @@ struct Geo {
   const Real* nw;          // [3][Np] wall normal (unit)
   const Real* cos_t;       // [Np]
   const Real* sin_t;       // [Np]
+  const Real* sb_fd;       // [nsb] fixed phase of the fictitious-density model, Eq. (24)
 };
 
 template <class Real>

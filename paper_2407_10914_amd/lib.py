@@ -29,7 +29,8 @@ EXPORTS = ("cg_options_default", "cg_lbm_create", "cg_lbm_destroy", "cg_last_err
            "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing", "cg_batch_create",
            "cg_batch_destroy", "cg_batch_step", "cg_batch_sync", "cg_batch_set_graph", "cg_batch_tune",
            "cg_batch_info", "cg_batch_observe", "cg_lbm_set_wetting", "cg_lbm_set_body_force", "cg_lbm_adjoint",
-           "cg_lbm_tune")
+           "cg_lbm_tune", "cg_lbm_set_pressure", "cg_lbm_switch_inlet", "cg_lbm_line_crossings",
+           "cg_lbm_drop_shape", "cg_batch_graph_captures", "cg_stream_probe")
 
 OBJECTIVES = {"saturation": 0, "red_volume": 1, "flux": 2}
 
@@ -81,6 +82,19 @@ class Info(C.Structure):
                                          "state_bytes", "device_bytes")] + \
                [("pull_bits", C.c_int), ("pull_fallback_bits", C.c_int), ("pull_waves", C.c_int64),
                 ("pull_waves_8bit", C.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Line(C.Structure):
+    _fields_ = [("axis", C.c_int), ("at", C.c_int * 3), ("lo", C.c_int), ("hi", C.c_int), ("blend_axis", C.c_int),
+                ("blend", C.c_double)]
+
+
+class Drop(C.Structure):
+    _fields_ = [("base", C.c_double), ("height", C.c_double), ("radius", C.c_double), ("theta_deg", C.c_double),
+                ("n_base_points", C.c_int)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -142,6 +156,13 @@ def load():
     L.cg_lbm_set_wetting.argtypes = [p, d, p]
     L.cg_lbm_set_body_force.argtypes = [p, C.POINTER(C.c_double)]
     L.cg_lbm_adjoint.argtypes = [p, C.POINTER(AdjointSpec), C.POINTER(Gradients)]
+    L.cg_lbm_set_pressure.argtypes = [p, d, d]
+    L.cg_lbm_switch_inlet.argtypes = [p, d]
+    L.cg_lbm_line_crossings.argtypes = [p, C.POINTER(Line), p, i, C.POINTER(i)]
+    L.cg_lbm_drop_shape.argtypes = [p, i, i, i, d, i, C.POINTER(Drop)]
+    L.cg_batch_graph_captures.argtypes = [p]
+    L.cg_batch_graph_captures.restype = i64
+    L.cg_stream_probe.argtypes = [i, p, p, C.c_size_t, i, i, i, p, i, C.POINTER(C.c_float)]
     L.cg_batch_create.argtypes = [p, i, C.POINTER(p)]
     L.cg_batch_destroy.argtypes = [p]
     L.cg_batch_destroy.restype = None

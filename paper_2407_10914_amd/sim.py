@@ -188,6 +188,43 @@ class Sim:
     def set_body_force(self, g):
         L.check(L.load().cg_lbm_set_body_force(self._h, (C.c_double * 3)(*[float(x) for x in g])))
 
+    def set_pressure(self, rho_in, rho_out):
+        """New Zou-He inlet/outlet densities for the following steps."""
+        L.check(L.load().cg_lbm_set_pressure(self._h, float(rho_in), float(rho_out)))
+
+    def switch_inlet(self, zeta_r):
+        """Inject the other fluid from now on (Eqs. 37-38): 1.0 = red, 0.0 = blue."""
+        L.check(L.load().cg_lbm_switch_inlet(self._h, float(zeta_r)))
+
+    # ------------------------------------------------------- interface points
+    def line_crossings(self, axis, at=(0, 0, 0), lo=0, hi=None, blend=0.0, blend_axis=0, max_points=256):
+        """phi = 0 crossings along one grid line (device side): the line along
+        `axis` through the voxel coordinates `at` (x, y, z; the entry on
+        `axis` is ignored), blended with the next line along `blend_axis`."""
+        n = (self.shape[2], self.shape[1], self.shape[0])
+        ln = L.Line(int(axis), (C.c_int * 3)(*[int(v) for v in at]), int(lo), int(n[axis] if hi is None else hi),
+                    int(blend_axis), float(blend))
+        pts = (C.c_double * max(1, max_points))()
+        cnt = C.c_int()
+        L.check(L.load().cg_lbm_line_crossings(self._h, C.byref(ln), pts, int(max_points), C.byref(cnt)))
+        return [pts[k] for k in range(min(cnt.value, max_points))]
+
+    def drop_shape(self, base_axis=0, wall_axis=1, slice=0, wall=0.5, row=1):
+        """Base, height, cap radius and angle (through the drop) of a sessile
+        drop, Eqs. 45-46, from the device phase field."""
+        d = L.Drop()
+        L.check(L.load().cg_lbm_drop_shape(self._h, int(base_axis), int(wall_axis), int(slice), float(wall), int(row),
+                                           C.byref(d)))
+        return d.as_dict()
+
+    def front(self, axis=2, at=None):
+        """First interface point from the low end along `axis` on one grid line
+        (default: the middle of the other axes), or nan."""
+        if at is None:
+            at = (self.shape[2] // 2, self.shape[1] // 2, self.shape[0] // 2)
+        xs = self.line_crossings(axis, at, max_points=1)
+        return xs[0] if xs else float("nan")
+
     # --------------------------------------------------------------- adjoint
     def adjoint(self, objective="saturation", *, n_steps, checkpoint_every=None, axis=2, lo=0, hi=1 << 30,
                 delta=0.0, field_grad=False):
@@ -290,6 +327,10 @@ class Batch:
         buf = C.create_string_buffer(4096)
         L.check(L.load().cg_batch_tune(self._h, int(reps), buf, 4096))
         return buf.value.decode()
+
+    @property
+    def graph_captures(self):
+        return L.load().cg_batch_graph_captures(self._h)
 
     def info(self):
         n = C.c_int64()

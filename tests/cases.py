@@ -63,3 +63,16 @@ def sessile_3d(edge, theta, scheme, sigma=1.0 / 45.0, beta=0.95):
     kw = dict(dim=3, periodic=c.periodic, tau_r=1.0, tau_b=1.0, sigma=sigma, beta=beta, scheme=scheme,
               theta_deg=theta, collision=1)
     return c, kw
+
+
+def outlet_slug(nz=40, radius=6.0, slug=(24, 34), scheme=2, theta=70.0, drho=0.05, zeta_r=0.0, n=16):
+    """A red slug in a blue-filled tube, pushed out through the Zou-He outlet
+    by a Type-I pressure difference: the outlet plane holds mixed phase
+    (chi^s strictly between 0 and 1, Eqs. B.12-B.18 with Eq. 39) for a few
+    hundred steps from about step 300."""
+    c = inputs.tube(nx=n, ny=n, nz=nz, radius=radius, wet_len=8)
+    z = np.arange(nz)[:, None, None]
+    c.phi0 = np.where((z >= slug[0]) & (z < slug[1]), 1.0, -1.0) * np.ones_like(c.phi0)
+    kw = dict(dim=3, periodic=c.periodic, tau_r=1.0, tau_b=1.0, sigma=1.0 / 45.0, beta=0.95, scheme=scheme,
+              theta_deg=theta, bc=1, rho_in=1.0 + drho, rho_out=1.0, zeta_r=zeta_r, collision=1)
+    return c, kw

@@ -85,7 +85,7 @@ def _create(L, so, *, dim=3, shape=(6, 6, 6), tau=(1.0, 1.0), sigma=0.01, beta=0
     (dict(tau=(1.0, 0.3)), "CG_EINVAL", b"tau"),
     (dict(beta=1.5), "CG_EINVAL", b"beta"),
     (dict(sigma=float("nan")), "CG_EINVAL", b"sigma"),
-    (dict(scheme=3), "CG_EINVAL", b"scheme"),
+    (dict(scheme=4), "CG_EINVAL", b"scheme"),
     (dict(theta=0.0), "CG_EINVAL", b"theta"),
     (dict(theta=180.0), "CG_EINVAL", b"theta"),
     (dict(dim=2, shape=(1, 6, 6), collision=1), "CG_EUNSUPPORTED", b"MRT"),

@@ -1,0 +1,226 @@
+"""GPU parity at the open faces and for the run-time boundary changes.
+
+* An interface leaving through the Zou-He outlet: a red slug pushed out of a
+  blue-filled tube, so the outlet plane holds mixed phase and the momentum
+  split chi^s of Eqs. (B.12)-(B.18) (with phi from Eq. 39) lies strictly
+  between 0 and 1.
+* Mixed injection at the inlet (zeta_r = 0.25, Eq. B.1).
+* The injected fluid switched in a running simulation (Eqs. 37-38) and the
+  Zou-He densities changed between pressure stages.
+* Fictitious-density wetting (Eq. 24).
+* Whole-run FP64 parity on the C2 capillary tube: a reduced tube over 5000
+  steps and the full 24x24x400 tube over 1000 steps.
+
+FP64 runs agree with the oracle to 1e-12 relative (they are bitwise equal);
+FP32 runs are compared one step at a time from the GPU's own state.
+"""
+import numpy as np
+import pytest
+
+from cases import c1_sessile_2d, c2_tube, outlet_slug, rel, rock
+from parity_helpers import TOL32, TOL64, compare_macro, fp32_step_from, gpu, orc, outlet_mixed, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("scheme,theta", [(2, 70.0), (1, 60.0)])
+def test_fp64_slug_leaving_through_the_outlet(scheme, theta):
+    case, kw = outlet_slug(scheme=scheme, theta=theta)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    mixed_seen = 0
+    for t in range(200, 1601, 200):
+        g.step(200)
+        o.step(200)
+        compare_macro(g, o, fluid, TOL64, f"slug S-{scheme} t={t}")
+        m = outlet_mixed(o.macro()["phi"], fluid)
+        assert outlet_mixed(g.field("phi"), fluid) == m
+        mixed_seen = max(mixed_seen, m)
+    # the interface did cross the outlet plane, and the red slug left
+    assert mixed_seen >= 30, mixed_seen
+    a, b = g.observe(), o.observe()
+    assert a["vol_r"] < 0.2 * ((case.phi0[fluid] + 1) / 2).sum()
+    for k in ("mass_r", "mass_b", "vol_r", "sat_nw_mass", "u_max"):
+        assert abs(a[k] - b[k]) <= 1e-12 * max(1.0, abs(b[k])), (k, a[k], b[k])
+
+
+def test_fp32_step_with_mixed_phase_on_the_outlet():
+    case, kw = outlet_slug()
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f32")
+    g.step(600)
+    m = outlet_mixed(g.field("phi"), fluid)
+    say("fp32 slug: mixed outlet nodes at t=600:", m)
+    assert m >= 30
+    fp32_step_from(g, case, kw, "slug fp32 600->601")
+
+
+def _mixed_injection_runs():
+    """zeta_r = 0.25: both colours enter with densities rho_in zeta^s
+    (Eq. B.1) and the inlet phase is phi_in = -0.5."""
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1", nz=40, radius=6.0, wet_len=12)
+    kw = dict(kw, zeta_r=0.25)
+    return case, kw
+
+
+def test_fp64_mixed_injection_against_the_oracle():
+    case, kw = _mixed_injection_runs()
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    for t in (100, 300):
+        n = t - g.time
+        g.step(n)
+        o.step(n)
+        compare_macro(g, o, fluid, TOL64, f"zeta 0.25 t={t}")
+    ph = g.field("phi")
+    assert np.all(ph[0][fluid[0]] == -0.5)
+    m = g.field("rho_r")
+    rho = m + g.field("rho_b")
+    assert np.abs(m[0][fluid[0]] / rho[0][fluid[0]] - 0.25).max() < 1e-12
+
+
+def test_fp32_step_mixed_injection():
+    case, kw = _mixed_injection_runs()
+    g = gpu(case, kw, "f32")
+    g.step(150)
+    fp32_step_from(g, case, kw, "zeta 0.25 fp32 150->151")
+
+
+@pytest.mark.parametrize("new", [0.0, 1.0])
+def test_fp64_switch_injected_fluid_against_the_oracle(new):
+    """Eqs. (37)-(38) in a running simulation: red injection (drainage) then
+    blue (imbibition), or the other way round."""
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1", nz=40, radius=6.0, wet_len=12)
+    kw = dict(kw, zeta_r=1.0 - new)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    g.step(120)
+    o.step(120)
+    g.switch_inlet(new)
+    o.switch_inlet(new)
+    compare_macro(g, o, fluid, TOL64, f"switch to {new} t=120")
+    gr, gb = g.populations()
+    orr, ob = o.get_state()
+    assert rel(gr, orr, fluid) <= TOL64 and rel(gb, ob, fluid) <= TOL64
+    for t in (121, 300):
+        n = t - g.time
+        g.step(n)
+        o.step(n)
+        compare_macro(g, o, fluid, TOL64, f"after switch t={t}")
+    assert g.time == 300
+
+
+@pytest.mark.parametrize("new", [0.0, 1.0])
+def test_fp32_switch_injected_fluid(new):
+    import oracle as O
+
+    case, kw = c2_tube(scheme=2, theta=45.0, drive="type1", nz=40, radius=6.0, wet_len=12)
+    kw = dict(kw, zeta_r=1.0 - new)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f32")
+    g.step(80)
+    fr, fb = g.populations()
+    o = O.OracleSim(case.solid, eps="f32", **kw)
+    o.set_state(fr, fb)
+    o.switch_inlet(new)
+    g.switch_inlet(new)
+    a, b = g.populations()
+    c, d = o.get_state()
+    say("fp32 switch populations", rel(a, c, fluid), rel(b, d, fluid))
+    assert rel(a, c, fluid) <= TOL32 and rel(b, d, fluid) <= TOL32
+    kw2 = dict(kw, zeta_r=new)
+    fp32_step_from(g, case, kw2, f"fp32 after switch to {new}")
+
+
+def test_fp64_pressure_stages_against_the_oracle():
+    """Zou-He densities changed twice during the run, as in the stages of a
+    drainage protocol (Sec. IV.B)."""
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1", nz=40, radius=6.0, wet_len=12)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    for rin, rout in ((1.03, 0.99), (1.0, 1.0)):
+        g.step(60)
+        o.step(60)
+        g.set_pressure(rin, rout)
+        o.set_pressure(rin, rout)
+    g.step(60)
+    o.step(60)
+    compare_macro(g, o, fluid, TOL64, "pressure stages t=180")
+
+
+def test_fp64_fictitious_density_wetting_2d_and_theta_field_rock():
+    case, kw = c1_sessile_2d()
+    kw = dict(kw, scheme=3, theta_deg=60.0)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    g.step(1000)
+    o.step(1000)
+    compare_macro(g, o, fluid, TOL64, "C1 fictitious density t=1000")
+    st = o.stages()
+    keep = o.setup_info()["cls"] >= 1
+    assert rel(g.field("phi"), st["phi"], keep) <= TOL64
+    case, kw = rock(n=32, buffer=4, drive="type2")
+    rng = np.random.default_rng(12)
+    th = np.where(case.solid == 1, rng.uniform(30.0, 150.0, case.solid.shape), 90.0)
+    kw = dict(kw, scheme=3, theta_field=th)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    g.step(60)
+    o.step(60)
+    compare_macro(g, o, fluid, TOL64, "rock32 fictitious density theta field t=60")
+
+
+def test_fp32_step_fictitious_density_rock():
+    case, kw = rock(n=40, buffer=4)
+    kw = dict(kw, scheme=3)
+    g = gpu(case, kw, "f32")
+    g.step(100)
+    fp32_step_from(g, case, kw, "rock40 fictitious density fp32 100->101")
+
+
+def test_fictitious_density_is_not_in_the_adjoint():
+    from paper_2407_10914_amd.lib import CgError
+
+    case, kw = c1_sessile_2d()
+    g = gpu(case, dict(kw, scheme=3), "f64")
+    with pytest.raises(CgError):
+        g.adjoint("saturation", n_steps=2, axis=0)
+
+
+def test_fp64_reduced_c2_tube_whole_run_5000_steps():
+    """A reduced capillary tube (r = 6, nz = 60), Type-I drive, Scheme-I at 45
+    degrees: bitwise with the oracle at every 500 steps through 5000."""
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1", nz=60, radius=6.0, wet_len=20)
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    for t in range(500, 5001, 500):
+        g.step(500)
+        o.step(500)
+        compare_macro(g, o, fluid, TOL64, f"reduced C2 t={t}")
+    gr, gb = g.populations()
+    orr, ob = o.get_state()
+    assert rel(gr, orr, fluid) <= TOL64 and rel(gb, ob, fluid) <= TOL64
+
+
+def test_fp64_c2_full_tube_1000_steps():
+    """The C2 tube at its full size (24x24x400, 126400 fluid nodes), Type-I,
+    Scheme-I 45 degrees: bitwise at steps 500 and 1000."""
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1")
+    fluid = case.solid == 0
+    g = gpu(case, kw, "f64")
+    o = orc(case, kw)
+    for t in (500, 1000):
+        g.step(500)
+        o.step(500)
+        compare_macro(g, o, fluid, TOL64, f"C2 full t={t}")
+    a = g.observe(axis=2, plane=200)
+    b = o.observe(axis=2, plane=200)
+    for k in ("mass_r", "mass_b", "vol_r", "vol_b", "flux_t", "flux_r", "flux_b", "sat_w", "sat_nw_mass"):
+        assert abs(a[k] - b[k]) <= 1e-12 * max(1.0, abs(b[k])), (k, a[k], b[k])
