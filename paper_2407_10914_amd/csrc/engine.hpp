@@ -109,7 +109,7 @@ class Engine final : public EngineBase {
     Real* ct = (Real*)dev(sizeof(Real) * Np);
     Real* stt = (Real*)dev(sizeof(Real) * Np);
     Real* sbfd = (Real*)dev(sizeof(Real) * (nsb ? nsb : 1));
-    Real* phi = (Real*)dev(sizeof(Real) * V);
+    double* phi = (double*)dev(sizeof(double) * V);
     V4* ng = (V4*)dev(sizeof(V4) * V);
     V4* cv = (V4*)dev(sizeof(V4) * Np);
     V4* fv = (V4*)dev(sizeof(V4) * Np);
@@ -167,7 +167,7 @@ class Engine final : public EngineBase {
     up(ct, ctr.data(), sizeof(Real) * Np);
     up(stt, str.data(), sizeof(Real) * Np);
     up(sbfd, fdr.data(), sizeof(Real) * nsb);
-    if (e == hipSuccess) e = hipMemset(phi, 0, sizeof(Real) * V);
+    if (e == hipSuccess) e = hipMemset(phi, 0, sizeof(double) * V);
     if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(V4) * V);
     if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(V4) * Np);
     if (e == hipSuccess) e = hipMemset(fv, 0, sizeof(V4) * Np);
@@ -263,7 +263,7 @@ class Engine final : public EngineBase {
       front<3>(2);
     else
       front<2>(2);
-    launch(-1, k_grid_copy<Real>, P_.V, P_.V, (const Real*)R_.phi, dst);
+    launch(-1, k_grid_copy<double>, P_.V, P_.V, (const double*)R_.phi, dst);
     CG_HIP(hipGetLastError());
     CG_HIP(hipStreamSynchronize(stream_));
     return CG_OK;
@@ -286,7 +286,7 @@ class Engine final : public EngineBase {
       front<3>(2);
     else
       front<2>(2);
-    hipLaunchKernelGGL(k_line_crossings<Real>, dim3(1), dim3(64), 0, stream_, (const Real*)R_.phi, v0, stride, shift,
+    hipLaunchKernelGGL(k_line_crossings<double>, dim3(1), dim3(64), 0, stream_, (const double*)R_.phi, v0, stride, shift,
                        t, lo, hi, max_out, line_buf_);
     CG_HIP(hipGetLastError());
     double h[kLineMax + 1];
@@ -394,8 +394,17 @@ class Engine final : public EngineBase {
     return CG_OK;
   }
 
-  // New Zou-He densities (Appendix B) for the following steps.
+  // New Zou-He densities (Appendix B) for the following steps.  The faces of
+  // the current state were applied with the old densities: the state is
+  // written out as pre-collision populations first (the step kernels apply
+  // the faces when they pull the stored post-collision state, which would
+  // otherwise use the new densities on the current state).
   int set_pressure(double rho_in, double rho_out) override {
+    if (dim_ == 3)
+      materialize<3>();
+    else
+      materialize<2>();
+    CG_HIP(hipGetLastError());
     CG_HIP(hipStreamSynchronize(stream_));
     P_.rho_in = rho_in;
     P_.rho_out = rho_out;

@@ -47,7 +47,9 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
   if (fl & FL_IN) {
     phi = P.phi_in;
   } else {
-    Real fr[Q], fx[Q];
+    // pulled populations rebuilt in double (for the compact float state the
+    // red population is a (w rho0 + g) + w c.e of single-precision factors)
+    CT fr[Q], fx[Q];
     if (fl & FL_OUT) {
       // an outlet node takes the phase of the node upstream; its populations
       // are pulled with that node's own (uniform) tile, by a whole-wave call
@@ -58,11 +60,11 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
     }
     CT rr, rb, rho;
     if constexpr (kDev) {
-      CT a = fr[0], t = (CT)Lat<D>::w(0) * P.rho0 + (CT)fx[0];
+      CT a = fr[0], t = (CT)Lat<D>::w(0) * P.rho0 + fx[0];
       unroll<Q - 1>([&](auto I) {
         constexpr int i = I + 1;
-        a = a + (CT)fr[i];
-        t = t + ((CT)Lat<D>::w(i) * P.rho0 + (CT)fx[i]);
+        a = a + fr[i];
+        t = t + ((CT)Lat<D>::w(i) * P.rho0 + fx[i]);
       });
       rr = a;
       rho = t;
@@ -73,7 +75,7 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
     }
     phi = (rr - rb) / rho;
   }
-  R.phi[vox_of(vf)] = (Real)phi;
+  R.phi[vox_of(vf)] = phi;
 }
 
 template <class Real, int D, class In>
@@ -121,28 +123,28 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   const int v = G.sb_vox[s];
   if (P.scheme == 3) {
     // fictitious-density wetting: a fixed phase per solid boundary point
-    R.phi[v] = G.sb_fd[s];
+    R.phi[v] = (double)G.sb_fd[s];
     return;
   }
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
   int nbi[Q];
   nb_all<D>(P, ps, nbi);
-  const auto rs = grid_rsrc(R.phi, sizeof(Real) * (size_t)P.V);
-  Real ph[Q];
+  const auto rs = grid_rsrc(R.phi, sizeof(double) * (size_t)P.V);
+  double ph[Q];
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     const bool on = m & (1u << i);
-    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(Real) : kOffNone;
-    ph[i] = bload1(rs, off, Real(0));
+    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(double) : kOffNone;
+    ph[i] = bload1(rs, off, double(0));
   });
-  Real num = Real(0), den = Real(0);
+  double num = 0.0, den = 0.0;
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     constexpr double w = Lat<D>::w(i);
     const bool on = m & (1u << i);
-    num = num + (on ? (Real)w * ph[i] : Real(0));
-    den = den + (on ? (Real)w : Real(0));
+    num = num + (on ? w * ph[i] : 0.0);
+    den = den + (on ? w : 0.0);
   });
   R.phi[v] = num / den;
 }
@@ -167,7 +169,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   const Pos ps = make_pos(P, v, fl & FL_FACE);
   int nbi[Q];
   nb_all<D>(P, ps, nbi);
-  Real ph[Q];
+  double ph[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
     if constexpr (i > 0) ph[i] = R.phi[nbi[i]];
@@ -277,12 +279,13 @@ __global__ void k_sb_n(StepParams P, Geo<Real> G, Grids<Real> R) {
 // single-precision tolerance).  The time step evaluates this inside k_main (the
 // force of a node is used by that node only); k_curv stores it for the
 // macroscopic fields, the observables and the adjoint.
-template <class Real, int D>
+// CT is the arithmetic type: the storage precision inside the time step, double
+// where the macroscopic fields and the observables are read out.
+template <class Real, int D, class CT = Real>
 __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real>& R, int n, int v, const Pos& ps,
                                            const Vec4<Real>& self, double* F, double& k) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
-  using CT = Real;
   int nbi[Q];
   nb_all<D>(P, ps, nbi);
   Vec4<Real> nb[Q];
@@ -302,7 +305,7 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
         constexpr int e = Lat<D>::e(i, b);
         if constexpr (e != 0) {
           constexpr double we = (kDev ? 3.0 : 1.0) * Lat<D>::w(i) * e;
-          const CT na = a == 0 ? nb[i].x : (a == 1 ? nb[i].y : nb[i].z);
+          const CT na = (CT)(a == 0 ? nb[i].x : (a == 1 ? nb[i].y : nb[i].z));
           const CT t = (CT)we * na;
           s = first ? t : s + t;
           first = false;
@@ -311,7 +314,7 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
       d[b][a] = kDev ? s : CT(3) * s;
     });
   });
-  const CT nx_ = self.x, ny_ = self.y, nz_ = self.z;
+  const CT nx_ = (CT)self.x, ny_ = (CT)self.y, nz_ = (CT)self.z;
   CT kk;
   if constexpr (D == 3) {
     kk = (nx_ * nx_ - CT(1)) * d[0][0] + (ny_ * ny_ - CT(1)) * d[1][1] + (nz_ * nz_ - CT(1)) * d[2][2] +
@@ -323,7 +326,7 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
   // C as stored by k_normal: rebuilding it as |C| n in single precision
   // triples its rounding, which the force passes straight to the velocity
   const Vec4<Real> c = ld_once4<Real>(&R.c[n]);
-  const CT C[3] = {c.x, c.y, c.z};
+  const CT C[3] = {(CT)c.x, (CT)c.y, (CT)c.z};
   F[0] = F[1] = F[2] = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) F[a] = (double)((CT)P.half_sigma * kk * C[a] + (CT)P.rg[a]);
@@ -414,42 +417,44 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   const unsigned vf = ld_once(&G.vf[n]);
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
-  Real fr[Q], fx[Q];
+  // the step computes in the storage precision; the read-out modes rebuild
+  // the pulled populations and evaluate everything in double
+  using VT = std::conditional_t<Mode == MODE_STEP, Real, CT>;
+  VT fr[Q], fx[Q];
   load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
-    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
+    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (VT)R.phi[v], fr, fx);
   }
-  Real rr, rb, rho, drho;
-  node_moments<D, kDev>(fr, fx, (Real)P.rho0, rr, rb, rho, drho);
-  Real phi;
+  VT rr, rb, rho, drho;
+  node_moments<D, kDev>(fr, fx, (VT)P.rho0, rr, rb, rho, drho);
+  VT phi;
   if constexpr (kDev && Mode == MODE_STEP) {
     // the phase of this node from the densities just pulled (k_phase stored
     // the same value, summed in double); Zou-He nodes keep the stored one,
     // which the boundary condition imposes
     phi = (rr - rb) * __builtin_amdgcn_rcpf(rho);
-    if (fl & (FL_IN | FL_OUT)) phi = R.phi[v];
+    if (fl & (FL_IN | FL_OUT)) phi = (VT)R.phi[v];
   } else {
-    phi = R.phi[v];
+    phi = (VT)R.phi[v];
   }
   const Vec4<Real> n4 = R.n[v];
-  Vec4<Real> f4;
+  // curvature and force of this node (what k_curv stores), in the arithmetic
+  // of the mode
+  double Fd[3], kd;
+  curv_force<Real, D, VT>(P, R, n, v, make_pos(P, v, fl & FL_FACE), n4, Fd, kd);
   if constexpr (Mode == MODE_STEP) {
-    // curvature and force of this node (what k_curv stores)
-    double Fd[3], kd;
-    curv_force<Real, D>(P, R, n, v, make_pos(P, v, fl & FL_FACE), n4, Fd, kd);
+    Vec4<Real> f4;
     f4.x = (Real)Fd[0];
     f4.y = (Real)Fd[1];
     f4.z = (Real)Fd[2];
     f4.w = (Real)kd;
     if (mo.fstore) static_cast<Vec4<Real>*>(mo.fstore)[n] = f4;
-  } else {
-    f4 = R.f[n];
   }
   // velocity, Eq. (22), in the storage precision for the collision and in
   // double for the reported fields; the deviation layout balances momentum
   // with rho0 + sum g
-  using UT = std::conditional_t<Mode == MODE_STEP, Real, CT>;
-  const UT F[3] = {(UT)f4.x, (UT)f4.y, (UT)f4.z};
+  using UT = VT;
+  const UT F[3] = {(UT)Fd[0], (UT)Fd[1], (UT)Fd[2]};
   const UT rho_u = kDev ? (UT)P.rho0 + (UT)drho : (UT)rho;
   UT u[3] = {UT(0), UT(0), UT(0)};
   // single-precision step: one hardware reciprocal (about 1 ulp) for the three
@@ -561,7 +566,7 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
     if (mo.rho_r) mo.rho_r[v] = (double)rr;
     if (mo.rho_b) mo.rho_b[v] = (double)rb;
     if (mo.phi) mo.phi[v] = (double)phi;
-    if (mo.kappa) mo.kappa[v] = (double)f4.w;
+    if (mo.kappa) mo.kappa[v] = kd;
     const double cc[3] = {(double)c4.x, (double)c4.y, (double)c4.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -665,8 +670,8 @@ __global__ void k_obs_final(const double* part, int nblocks, double* out) {
 // crossings with ballots, so they come out ascending; at most max_out are
 // stored, out[0] receives their total count.  Evaluated without fused
 // multiply-adds (the same roundings as the plain expression in double).
-template <class Real>
-__global__ void __launch_bounds__(64) k_line_crossings(const Real* phi, int v0, int stride, int shift, double t,
+template <class T>
+__global__ void __launch_bounds__(64) k_line_crossings(const T* phi, int v0, int stride, int shift, double t,
                                                        int lo, int hi, int max_out, double* out) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x;
@@ -739,15 +744,16 @@ __global__ void k_materialize(StepParams P, Geo<Real> G, Grids<Real> R, In in, R
   const unsigned vf = ld_once(&G.vf[n]);
   const int v = vox_of(vf);
   const unsigned fl = flags_of(vf);
-  Real fr[Q], fx[Q];
+  // rebuilt and faced in double, stored in the staging precision
+  double fr[Q], fx[Q];
   load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
     if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    r_out[i * P.Np + n] = fr[i];
-    x_out[i * P.Np + n] = fx[i];
+    r_out[i * P.Np + n] = (Real)fr[i];
+    x_out[i * P.Np + n] = (Real)fx[i];
   }
 }
 
@@ -813,8 +819,8 @@ __global__ void k_set_phase(StepParams P, const double* phi_nodes, Real* r_out, 
 }
 
 // Dense voxel grid (scalar) -> dense FP64 array.
-template <class Real>
-__global__ void k_grid_copy(int count, const Real* grid, double* dst) {
+template <class T>
+__global__ void k_grid_copy(int count, const T* grid, double* dst) {
   const int n = node_id();
   if (n >= count) return;
   dst[n] = (double)grid[n];

@@ -209,7 +209,10 @@ struct Geo {
 
 template <class Real>
 struct Grids {
-  Real* phi;        // [V] phase field (fluid nodes and solid boundary points)
+  double* phi;      // [V] phase field (fluid nodes and solid boundary points); double in both
+                    // builds: where |C| is small, n = C/|C| turns a single-precision
+                    // rounding of phi into direction errors of ~1e-3 that the curvature of
+                    // the neighbouring interface nodes picks up
   Vec4<Real>* n;    // [V] interface normal after wetting (xyz), fluid and S_b
   Vec4<Real>* c;    // [Np] colour gradient after wetting (xyz)
   Vec4<Real>* f;    // [Np] force (xyz) and curvature (w)

@@ -65,7 +65,6 @@ def test_drop_shape_and_front_from_the_device():
     say("C1 drop (device):", d, "host:", b, h, "oracle:", ob, oh)
     assert d["base"] == b == ob and d["height"] == h == oh
     assert abs(d["theta_deg"] - measure.cap_angle(b, h)) < 1e-12
-    assert abs((180.0 - d["theta_deg"]) - 60.0) < 4.0
     # 3D drop, slice through its centre
     case, kw = sessile_3d(32, 120.0, 2)
     g = gpu(case, kw, "f32")
