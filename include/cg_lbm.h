@@ -200,6 +200,20 @@ typedef struct {
  * still filled). */
 cg_status cg_lbm_observe(cg_lbm* h, int axis, int plane, cg_observables* out);
 
+/* cg_lbm_observe for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same reductions and results, with the per-block partial sums and the
+ * final sums kept in a 4 MiB array that the library holds in static device
+ * memory on every device it runs on (until the process ends), instead of
+ * memory the run allocated.  The call allocates nothing (no hipMalloc, no
+ * allocator callback).  Limit: runs of at most 8,947,456 fluid nodes (one
+ * partial record of 15 doubles per block of 256 nodes must fit); larger runs
+ * get CG_EINVAL and a message.  All calls on one device share that device's
+ * array, so calls that overlap on one device (other threads, other handles)
+ * race; calls on one handle are serialised anyway.  Synchronises the stream.
+ * Returns CG_EUNSTABLE if nan_count > 0 (out is still filled). */
+cg_status cg_lbm_observe_noalloc(cg_lbm* h, int axis, int plane, cg_observables* out);
+
 enum {
   CG_FIELD_RHO_R = 0, /* [V] */
   CG_FIELD_RHO_B = 1, /* [V] */
@@ -249,7 +263,7 @@ cg_status cg_lbm_load(cg_lbm* h, const void* src);
  * cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n, k_curv,
  * k_main; -1 = all, 0 = off).  A time step runs k_phase, k_sb_phi, k_normal,
  * k_sb_n and k_main (which evaluates the curvature and force of its node);
- * k_curv stores them before the macroscopic fields and the observables.
+ * k_curv stores them for the reverse steps of the adjoint.
  * cg_lbm_kernel_times synchronises, then reports for each kernel its name,
  * launch count and total milliseconds since the last reset (n: in =
  * capacity, out = count). */

@@ -25,6 +25,7 @@ SOURCES = [
     ("setup.cpp", ["-x", "hip", "-ffp-contract=off"]),
     ("capi.hip", []),
     ("probe.hip", []),
+    ("noalloc.hip", []),
 ]
 
 

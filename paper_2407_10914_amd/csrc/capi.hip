@@ -10,6 +10,7 @@
 #include "../../include/cg_lbm.h"
 #include "batch_base.hpp"
 #include "engine_base.hpp"
+#include "handle.hpp"
 #include "setup.hpp"
 
 namespace {
@@ -20,14 +21,7 @@ cg_status fail(cg_status s, const std::string& m) {
 }
 }  // namespace
 
-struct cg_lbm {
-  cg::HostSetup S;
-  cg::StepParams P{};
-  cg::Alloc al;
-  std::unique_ptr<cg::EngineBase> eng;
-  hipStream_t stream = nullptr;
-  int device = 0, precision = CG_FP32, collision = CG_MRT;
-};
+cg_status cg::set_error(cg_status s, const std::string& msg) { return fail(s, msg); }
 
 namespace {
 
@@ -193,25 +187,8 @@ cg_status cg_lbm_observe(cg_lbm* h, int axis, int plane, cg_observables* out) {
   double o[cg::kObsN];
   int rc = h->eng->observe(axis, plane, o);
   if (rc != CG_OK) return engine_status(h, rc);
-  std::memset(out, 0, sizeof(*out));
-  out->step = h->eng->t;
-  out->mass_r = o[0];
-  out->mass_b = o[1];
-  out->n_fluid = o[2];
-  out->sat_w = o[2] > 0 ? o[3] / o[2] : 0.0;
-  out->sat_nw_mass = (o[0] + o[1]) > 0 ? o[0] / (o[0] + o[1]) : 0.0;
-  out->vol_r = o[4];
-  out->vol_b = o[5];
-  out->p_in = o[7] > 0 ? o[6] / o[7] : 0.0;
-  out->n_in = o[7];
-  out->p_out = o[9] > 0 ? o[8] / o[9] : 0.0;
-  out->n_out = o[9];
-  out->u_max = o[10];
-  out->nan_count = o[11];
-  out->flux_t = o[12];
-  out->flux_r = o[13];
-  out->flux_b = o[14];
-  if (o[11] > 0) return fail(CG_EUNSTABLE, "non-finite density or velocity in the state");
+  if (cg::fill_observables(o, h->eng->t, out) > 0)
+    return fail(CG_EUNSTABLE, "non-finite density or velocity in the state");
   return CG_OK;
 }
 

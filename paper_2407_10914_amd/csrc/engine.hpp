@@ -307,18 +307,23 @@ class Engine final : public EngineBase {
     return CG_OK;
   }
 
-  int observe(int axis, int plane, double* out) override {
+  int observe(int axis, int plane, double* out) override { return observe_into(axis, plane, obs_part_, obs_out_, out); }
+
+  // The observables with caller-given device buffers for the per-block
+  // partial sums (obs_partials() doubles) and the kObsN final sums.
+  int observe_into(int axis, int plane, double* part, double* sums, double* out) override {
     P_.flux_axis = axis;
     P_.flux_plane = plane;
     if (dim_ == 3)
-      run_obs<3>();
+      run_obs<3>(part, sums);
     else
-      run_obs<2>();
+      run_obs<2>(part, sums);
     CG_HIP(hipGetLastError());
-    CG_HIP(hipMemcpyAsync(out, obs_out_, sizeof(double) * kObsN, hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipMemcpyAsync(out, sums, sizeof(double) * kObsN, hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipStreamSynchronize(stream_));
     return CG_OK;
   }
+  size_t obs_partials() const override { return (size_t)kObsN * (size_t)((P_.N + BS - 1) / BS); }
 
   // snapshot: header (time, pre flag, cur) + the live state buffers
   size_t snapshot_bytes() const override { return 64 + state_bytes_ + pre_bytes(); }
@@ -712,7 +717,7 @@ class Engine final : public EngineBase {
 
   template <int D, class In>
   void macro_with(const In& in, MacroOut mo) {
-    front_with<D>(in, 5);
+    front_with<D>(in, 4);
     auto out = out_next<D>();
     launch(-1, k_main<Real, D, BS, MODE_MACRO, In, decltype(out)>, P_.N, P_, G_, R_, in, out, mo, ObsOut{});
   }
@@ -725,21 +730,20 @@ class Engine final : public EngineBase {
   }
 
   template <int D, class In>
-  void obs_with(const In& in) {
-    front_with<D>(in, 5);
+  void obs_with(const In& in, double* part, double* sums) {
+    front_with<D>(in, 4);
     auto out = out_next<D>();
     const int nb = (P_.N + BS - 1) / BS;
     launch(-1, k_main<Real, D, BS, MODE_OBS, In, decltype(out)>, P_.N, P_, G_, R_, in, out, MacroOut{},
-           ObsOut{obs_part_});
-    hipLaunchKernelGGL(k_obs_final<Real>, dim3(kObsN), dim3(256), 0, stream_, (const double*)obs_part_, nb,
-                       obs_out_);
+           ObsOut{part});
+    hipLaunchKernelGGL(k_obs_final<Real>, dim3(kObsN), dim3(256), 0, stream_, (const double*)part, nb, sums);
   }
   template <int D>
-  void run_obs() {
+  void run_obs(double* part, double* sums) {
     if (pre_)
-      obs_with<D>(in_pre<D>());
+      obs_with<D>(in_pre<D>(), part, sums);
     else
-      obs_with<D>(in_post<D>());
+      obs_with<D>(in_post<D>(), part, sums);
   }
 
   template <int D, class In>

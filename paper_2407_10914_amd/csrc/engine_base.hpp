@@ -56,6 +56,9 @@ struct EngineBase {
   virtual int n_grid(double* dst) = 0;
   virtual int export_pops(double* fr, double* fb) = 0;
   virtual int observe(int axis, int plane, double* out) = 0;
+  virtual int observe_into(int axis, int plane, double* part, double* sums, double* out) = 0;
+  // doubles of per-block partial sums that observe_into needs
+  virtual size_t obs_partials() const = 0;
   virtual size_t snapshot_bytes() const = 0;
   virtual int save(void* dst) = 0;
   virtual int load(const void* src) = 0;
