@@ -253,7 +253,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     });
     rho = t;
     drho = sg;
-    rr = rho * (CT(1) + (CT)R.phi[v]) * CT(0.5);
+    rr = rho * (CT(1) + (CT)phi_dec(R.phi[v])) * CT(0.5);
     rb = rho - rr;
   } else {
     Real fr[Q], fx[Q];
@@ -277,7 +277,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   const CT F[3] = {(CT)f4.x, (CT)f4.y, (CT)f4.z};
   const CT kap = (CT)f4.w;
   const CT nv[3] = {(CT)n4.x, (CT)n4.y, (CT)n4.z};
-  const CT phi = (CT)R.phi[v];
+  const CT phi = (CT)phi_dec(R.phi[v]);
   CT u[3] = {CT(0), CT(0), CT(0)};
   unroll<D>([&](auto A_) {
     constexpr int a = A_;
@@ -773,7 +773,7 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
   CT C[3] = {CT(0), CT(0), CT(0)};
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
-    const CT ph = (CT)R.phi[nbi[j]];
+    const CT ph = (CT)phi_dec(R.phi[nbi[j]]);
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
       constexpr int e = Lat<D>::e(j, a);

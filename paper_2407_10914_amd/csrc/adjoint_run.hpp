@@ -212,7 +212,7 @@ class AdjointRun {
       bool gok = true;
       const size_t m0 = mem_.size(), b0 = bytes_;
       for (auto& x : g) {
-        x.phi = (double*)get(sizeof(double) * V);
+        x.phi = (typename Grids<Real>::PhiT*)get(sizeof(typename Grids<Real>::PhiT) * V);
         x.n = (V4*)get(sizeof(V4) * V);
         x.c = (V4*)get(sizeof(V4) * Np);
         x.f = (V4*)get(sizeof(V4) * Np);
@@ -266,7 +266,7 @@ class AdjointRun {
     zero(sums_, sizeof(double) * 8);
     // grid voxels that no stage writes (interior solid) are read as zeros
     for (auto& x : fg_) {
-      zero(x.phi, sizeof(double) * V);
+      if (e == hipSuccess) e = Engine<Real>::fill_phi_zero(x.phi, V, st);
       zero(x.n, sizeof(V4) * V);
     }
     if (e != hipSuccess) {

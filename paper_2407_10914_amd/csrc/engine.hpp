@@ -109,7 +109,8 @@ class Engine final : public EngineBase {
     Real* ct = (Real*)dev(sizeof(Real) * Np);
     Real* stt = (Real*)dev(sizeof(Real) * Np);
     Real* sbfd = (Real*)dev(sizeof(Real) * (nsb ? nsb : 1));
-    double* phi = (double*)dev(sizeof(double) * V);
+    using PhiT = typename Grids<Real>::PhiT;
+    PhiT* phi = (PhiT*)dev(sizeof(PhiT) * V);
     V4* ng = (V4*)dev(sizeof(V4) * V);
     V4* cv = (V4*)dev(sizeof(V4) * Np);
     V4* fv = (V4*)dev(sizeof(V4) * Np);
@@ -167,7 +168,8 @@ class Engine final : public EngineBase {
     up(ct, ctr.data(), sizeof(Real) * Np);
     up(stt, str.data(), sizeof(Real) * Np);
     up(sbfd, fdr.data(), sizeof(Real) * nsb);
-    if (e == hipSuccess) e = hipMemset(phi, 0, sizeof(double) * V);
+    // voxels that no stage writes (interior solid) hold phi = 0
+    if (e == hipSuccess) e = fill_phi_zero(phi, V, nullptr);
     if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(V4) * V);
     if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(V4) * Np);
     if (e == hipSuccess) e = hipMemset(fv, 0, sizeof(V4) * Np);
@@ -263,7 +265,8 @@ class Engine final : public EngineBase {
       front<3>(2);
     else
       front<2>(2);
-    launch(-1, k_grid_copy<double>, P_.V, P_.V, (const double*)R_.phi, dst);
+    using PhiT = typename Grids<Real>::PhiT;
+    launch(-1, k_grid_copy<PhiT>, P_.V, P_.V, (const PhiT*)R_.phi, dst);
     CG_HIP(hipGetLastError());
     CG_HIP(hipStreamSynchronize(stream_));
     return CG_OK;
@@ -286,7 +289,8 @@ class Engine final : public EngineBase {
       front<3>(2);
     else
       front<2>(2);
-    hipLaunchKernelGGL(k_line_crossings<double>, dim3(1), dim3(64), 0, stream_, (const double*)R_.phi, v0, stride, shift,
+    using PhiT = typename Grids<Real>::PhiT;
+    hipLaunchKernelGGL(k_line_crossings<PhiT>, dim3(1), dim3(64), 0, stream_, (const PhiT*)R_.phi, v0, stride, shift,
                        t, lo, hi, max_out, line_buf_);
     CG_HIP(hipGetLastError());
     double h[kLineMax + 1];
@@ -546,6 +550,18 @@ class Engine final : public EngineBase {
     if (n & 1) cur_ ^= 1;
     t += n;
     if (n) pre_ = false;
+  }
+
+  // phase-field grid set to phi = 0 (the encoded zero in single precision);
+  // synchronous when s is null
+  static hipError_t fill_phi_zero(typename Grids<Real>::PhiT* p, size_t count, hipStream_t s) {
+    if constexpr (kF32) {
+      // phi = 0: d = -1.0f, choice bit 0
+      const auto d = reinterpret_cast<hipDeviceptr_t>(p);
+      return s ? hipMemsetD32Async(d, 0xBF800000u, count, s) : hipMemsetD32(d, 0xBF800000u, count);
+    } else {
+      return s ? hipMemsetAsync(p, 0, sizeof(double) * count, s) : hipMemset(p, 0, sizeof(double) * count);
+    }
   }
 
  private:

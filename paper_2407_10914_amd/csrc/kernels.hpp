@@ -75,7 +75,7 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
     }
     phi = (rr - rb) / rho;
   }
-  R.phi[vox_of(vf)] = phi;
+  R.phi[vox_of(vf)] = phi_enc<typename Grids<Real>::PhiT>(phi);
 }
 
 template <class Real, int D, class In>
@@ -123,20 +123,21 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   const int v = G.sb_vox[s];
   if (P.scheme == 3) {
     // fictitious-density wetting: a fixed phase per solid boundary point
-    R.phi[v] = (double)G.sb_fd[s];
+    R.phi[v] = phi_enc<typename Grids<Real>::PhiT>((double)G.sb_fd[s]);
     return;
   }
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
   int nbi[Q];
   nb_all<D>(P, ps, nbi);
-  const auto rs = grid_rsrc(R.phi, sizeof(double) * (size_t)P.V);
+  using PhiT = typename Grids<Real>::PhiT;
+  const auto rs = grid_rsrc(R.phi, sizeof(PhiT) * (size_t)P.V);
   double ph[Q];
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     const bool on = m & (1u << i);
-    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(double) : kOffNone;
-    ph[i] = bload1(rs, off, double(0));
+    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(PhiT) : kOffNone;
+    ph[i] = phi_dec(bload1(rs, off, PhiT(0)));
   });
   double num = 0.0, den = 0.0;
   unroll<Q - 1>([&](auto I) {
@@ -146,7 +147,7 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
     num = num + (on ? w * ph[i] : 0.0);
     den = den + (on ? w : 0.0);
   });
-  R.phi[v] = num / den;
+  R.phi[v] = phi_enc<PhiT>(num / den);
 }
 
 template <class Real, int D>
@@ -172,7 +173,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   double ph[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
-    if constexpr (i > 0) ph[i] = R.phi[nbi[i]];
+    if constexpr (i > 0) ph[i] = phi_dec(R.phi[nbi[i]]);
   });
   CT C[3] = {CT(0), CT(0), CT(0)};
   unroll<D>([&](auto A_) {
@@ -423,20 +424,19 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   VT fr[Q], fx[Q];
   load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
-    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (VT)R.phi[v], fr, fx);
+    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (VT)phi_dec(R.phi[v]), fr, fx);
   }
   VT rr, rb, rho, drho;
   node_moments<D, kDev>(fr, fx, (VT)P.rho0, rr, rb, rho, drho);
+  // the phase of this node from the densities just pulled (k_phase stored
+  // the same value, summed in double); Zou-He nodes keep the stored one,
+  // which the boundary condition imposes
   VT phi;
-  if constexpr (kDev && Mode == MODE_STEP) {
-    // the phase of this node from the densities just pulled (k_phase stored
-    // the same value, summed in double); Zou-He nodes keep the stored one,
-    // which the boundary condition imposes
+  if constexpr (kDev && Mode == MODE_STEP)
     phi = (rr - rb) * __builtin_amdgcn_rcpf(rho);
-    if (fl & (FL_IN | FL_OUT)) phi = (VT)R.phi[v];
-  } else {
-    phi = (VT)R.phi[v];
-  }
+  else
+    phi = (rr - rb) / rho;
+  if (fl & (FL_IN | FL_OUT)) phi = (VT)phi_dec(R.phi[v]);
   const Vec4<Real> n4 = R.n[v];
   // curvature and force of this node (what k_curv stores), in the arithmetic
   // of the mode
@@ -682,9 +682,9 @@ __global__ void __launch_bounds__(64) k_line_crossings(const T* phi, int v0, int
     bool hit = false;
     if (k < hi) {
       auto prof = [&](int kk) {
-        const double a = (double)phi[v0 + kk * stride];
+        const double a = phi_dec(phi[v0 + kk * stride]);
         if (t == 0.0) return a;
-        const double b = (double)phi[v0 + shift + kk * stride];
+        const double b = phi_dec(phi[v0 + shift + kk * stride]);
         return (1.0 - t) * a + t * b;
       };
       const double a = prof(k);
@@ -723,7 +723,7 @@ __global__ void k_export(StepParams P, Geo<Real> G, Grids<Real> R, In in, double
   double fr[Q], fx[Q];
   load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
-    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (double)R.phi[v], fr, fx);
+    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, phi_dec(R.phi[v]), fr, fx);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -748,7 +748,7 @@ __global__ void k_materialize(StepParams P, Geo<Real> G, Grids<Real> R, In in, R
   double fr[Q], fx[Q];
   load_node<D>(in, G.nbr, n, fr, fx);
   if constexpr (In::kPull) {
-    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, R.phi[v], fr, fx);
+    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, phi_dec(R.phi[v]), fr, fx);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -818,12 +818,12 @@ __global__ void k_set_phase(StepParams P, const double* phi_nodes, Real* r_out, 
   });
 }
 
-// Dense voxel grid (scalar) -> dense FP64 array.
+// Phase-field grid (stored as PhiStore) -> dense FP64 array.
 template <class T>
 __global__ void k_grid_copy(int count, const T* grid, double* dst) {
   const int n = node_id();
   if (n >= count) return;
-  dst[n] = (double)grid[n];
+  dst[n] = phi_dec(grid[n]);
 }
 
 // Dense voxel grid of 4-vectors -> dense FP64 [3][V] array.

@@ -207,12 +207,46 @@ struct Geo {
   const Real* sb_fd;       // [nsb] fixed phase of the fictitious-density model, Eq. (24)
 };
 
+// Storage of the phase-field grid.  Double precision stores phi itself.
+// Single precision stores d = phi - 1 (phi >= 0) or d = phi + 1 (phi < 0)
+// rounded to float, with the lowest mantissa bit replaced by the choice
+// (1: phi < 0).  Near the bulk, where |C| is small and n = C/|C| would turn
+// a rounding of phi near +-1 (6e-8 in float) into a direction error of up
+// to ~1e-3 that the curvature of neighbouring interface nodes picks up, the
+// stored value keeps relative precision in phi -+ 1 (at most one unit in the
+// last place of d, also past +-1, where rounding can take phi).  Decoding is
+// exact in double.
+template <class Real>
+struct PhiStore;
+template <>
+struct PhiStore<double> {
+  using type = double;
+};
+template <>
+struct PhiStore<float> {
+  using type = float;
+};
+__device__ __forceinline__ double phi_dec(double s) { return s; }
+__device__ __forceinline__ double phi_dec(float s) {
+  return (__builtin_bit_cast(uint32_t, s) & 1u) ? (double)s - 1.0 : (double)s + 1.0;
+}
+template <class T>
+__device__ __forceinline__ T phi_enc(double p);
+template <>
+__device__ __forceinline__ double phi_enc<double>(double p) {
+  return p;
+}
+template <>
+__device__ __forceinline__ float phi_enc<float>(double p) {
+  const bool neg = p < 0.0;
+  const float d = (float)(neg ? p + 1.0 : p - 1.0);
+  return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, d) & ~1u) | (neg ? 1u : 0u));
+}
+
 template <class Real>
 struct Grids {
-  double* phi;      // [V] phase field (fluid nodes and solid boundary points); double in both
-                    // builds: where |C| is small, n = C/|C| turns a single-precision
-                    // rounding of phi into direction errors of ~1e-3 that the curvature of
-                    // the neighbouring interface nodes picks up
+  using PhiT = typename PhiStore<Real>::type;
+  PhiT* phi;        // [V] phase field (fluid nodes and solid boundary points), see PhiStore
   Vec4<Real>* n;    // [V] interface normal after wetting (xyz), fluid and S_b
   Vec4<Real>* c;    // [Np] colour gradient after wetting (xyz)
   Vec4<Real>* f;    // [Np] force (xyz) and curvature (w)
