@@ -200,6 +200,14 @@ typedef struct {
  * still filled). */
 cg_status cg_lbm_observe(cg_lbm* h, int axis, int plane, cg_observables* out);
 
+/* The reductions of cg_lbm_observe restricted to the fluid nodes with
+ * lo <= coordinate[slab_axis] < hi (for example the porous sample between
+ * the inlet and outlet buffer layers, over which Sec. IV.B counts the
+ * wetting saturation); the plane flux (axis, plane) is still summed over its
+ * whole plane.  CG_EINVAL for an empty or out-of-box slab; CG_EUNSTABLE if a
+ * node of the slab is not finite.  Synchronises the stream. */
+cg_status cg_lbm_observe_slab(cg_lbm* h, int slab_axis, int lo, int hi, int axis, int plane, cg_observables* out);
+
 /* cg_lbm_observe for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same reductions and results, with the per-block partial sums and the

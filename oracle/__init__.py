@@ -71,6 +71,7 @@ def lib():
         L.orc_macro.argtypes = [p, p, p, p, p]
         L.orc_stages.argtypes = [p, p, p, p, p, p]
         L.orc_observe.argtypes = [p, i, i, C.POINTER(Obs)]
+        L.orc_observe_slab.argtypes = [p, i, i, i, i, i, C.POINTER(Obs)]
         L.orc_setup_info.argtypes = [p, p, p, p, p, p]
         L.orc_lattice.argtypes = [i, p, p, p]
         L.orc_mrt_matrix.argtypes = [p, p]
@@ -298,9 +299,15 @@ class OracleSim:
     def set_body_force(self, g):
         _check(lib().orc_set_body_force(self._h, _ptr(_f64(g, 3))))
 
-    def observe(self, axis=2, plane=0):
+    def observe(self, axis=2, plane=0, slab=None):
+        """Observables; slab = (axis, lo, hi) restricts them (not the plane flux)
+        to the fluid nodes with lo <= coordinate < hi."""
         o = Obs()
-        _check(lib().orc_observe(self._h, axis, plane, C.byref(o)))
+        if slab is None:
+            _check(lib().orc_observe(self._h, axis, plane, C.byref(o)))
+        else:
+            _check(lib().orc_observe_slab(self._h, int(slab[0]), int(slab[1]), int(slab[2]), axis, plane,
+                                          C.byref(o)))
         return o.as_dict()
 
     def setup_info(self):

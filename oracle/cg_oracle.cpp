@@ -996,7 +996,10 @@ struct Sim {
     return which == 0 ? sr / st : vr;
   }
 
-  void observe(int axis, int plane, orc_obs* o) {
+  /* Observables over the fluid nodes with slab_lo <= coordinate[slab_axis] <
+   * slab_hi (slab_axis < 0: all fluid nodes); the plane flux is taken over
+   * its whole plane. */
+  void observe(int axis, int plane, orc_obs* o, int slab_axis = -1, long slab_lo = 0, long slab_hi = 0) {
     macro();
     std::memset(o, 0, sizeof(*o));
     double sr = 0, sb = 0, nfl = 0, nw = 0, vr = 0, vb = 0, pin = 0, pout = 0, nin = 0, nout = 0, umax = 0,
@@ -1011,10 +1014,20 @@ struct Sim {
         ok = ok && std::isfinite(uc);
         u2 += uc * uc;
       }
+      long c[3];
+      coords(v, c);
+      const bool in_slab = slab_axis < 0 || (c[slab_axis] >= slab_lo && c[slab_axis] < slab_hi);
       if (!ok) {
-        nan += 1;
+        if (in_slab) nan += 1;
         continue;
       }
+      if (axis >= 0 && axis < D && c[axis] == plane) {
+        const double ua = val(uvel[axis * V + v]);
+        ft += (a + b) * ua;
+        fr_ += a * ua;
+        fb_ += b * ua;
+      }
+      if (!in_slab) continue;
       nfl += 1;
       sr += a;
       sb += b;
@@ -1032,14 +1045,6 @@ struct Sim {
       }
       const double um = std::sqrt(u2);
       if (um > umax) umax = um;
-      long c[3];
-      coords(v, c);
-      if (axis >= 0 && axis < D && c[axis] == plane) {
-        const double ua = val(uvel[axis * V + v]);
-        ft += (a + b) * ua;
-        fr_ += a * ua;
-        fb_ += b * ua;
-      }
     }
     o->mass_r = sr;
     o->mass_b = sb;
@@ -1180,6 +1185,13 @@ int orc_set_body_force(orc_sim* s, const double* g3) {
 int orc_observe(orc_sim* s, int axis, int plane, orc_obs* out) {
   if (!s || !out) return fail("null argument");
   s->s.observe(axis, plane, out);
+  return 0;
+}
+
+int orc_observe_slab(orc_sim* s, int slab_axis, int lo, int hi, int axis, int plane, orc_obs* out) {
+  if (!s || !out) return fail("null argument");
+  if (slab_axis < 0 || slab_axis >= s->s.D) return fail("bad slab axis");
+  s->s.observe(axis, plane, out, slab_axis, lo, hi);
   return 0;
 }
 

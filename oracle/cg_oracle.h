@@ -81,6 +81,9 @@ int orc_set_pressure(orc_sim* s, double rho_in, double rho_out);
 int orc_set_body_force(orc_sim* s, const double* g3);
 /* axis: 0/1/2; plane: index on that axis */
 int orc_observe(orc_sim* s, int axis, int plane, orc_obs* out);
+/* The same over the fluid nodes with lo <= coordinate[slab_axis] < hi (the
+ * plane flux still over its whole plane). */
+int orc_observe_slab(orc_sim* s, int slab_axis, int lo, int hi, int axis, int plane, orc_obs* out);
 /* cls: 0 interior solid, 1 S_b, 2 fluid, 3 F_b.  g3: smoothed image; nw3: [3][V];
  * cos_t/sin_t: contact angle at F_b nodes. */
 int orc_setup_info(const orc_sim* s, uint8_t* cls, double* g3, double* nw3,

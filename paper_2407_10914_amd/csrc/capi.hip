@@ -144,6 +144,8 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   P.eps_v = o.eps_v;
   P.flux_axis = -1;
   P.flux_plane = 0;
+  P.slab_axis = -1;
+  P.slab_lo = P.slab_hi = 0;
   h->eng.reset(o.precision == CG_FP64 ? cg::make_engine_f64() : cg::make_engine_f32());
   rc = h->eng->init(S, P, o.block, &h->al, h->stream, &err);
   if (rc != CG_OK) {
@@ -189,6 +191,19 @@ cg_status cg_lbm_observe(cg_lbm* h, int axis, int plane, cg_observables* out) {
   if (rc != CG_OK) return engine_status(h, rc);
   if (cg::fill_observables(o, h->eng->t, out) > 0)
     return fail(CG_EUNSTABLE, "non-finite density or velocity in the state");
+  return CG_OK;
+}
+
+cg_status cg_lbm_observe_slab(cg_lbm* h, int slab_axis, int lo, int hi, int axis, int plane, cg_observables* out) {
+  if (!h || !out) return fail(CG_EINVAL, "NULL argument");
+  const int n[3] = {h->S.nx, h->S.ny, h->S.nz};
+  if (slab_axis < 0 || slab_axis >= h->S.dim || lo < 0 || hi <= lo || hi > n[slab_axis])
+    return fail(CG_EINVAL, "bad slab");
+  double o[cg::kObsN];
+  int rc = h->eng->observe_slab(axis, plane, slab_axis, lo, hi, o);
+  if (rc != CG_OK) return engine_status(h, rc);
+  if (cg::fill_observables(o, h->eng->t, out) > 0)
+    return fail(CG_EUNSTABLE, "non-finite density or velocity in the slab");
   return CG_OK;
 }
 

@@ -311,13 +311,23 @@ class Engine final : public EngineBase {
     return CG_OK;
   }
 
-  int observe(int axis, int plane, double* out) override { return observe_into(axis, plane, obs_part_, obs_out_, out); }
+  int observe(int axis, int plane, double* out) override {
+    return observe_into(axis, plane, -1, 0, 0, obs_part_, obs_out_, out);
+  }
+  int observe_slab(int axis, int plane, int slab_axis, int lo, int hi, double* out) override {
+    return observe_into(axis, plane, slab_axis, lo, hi, obs_part_, obs_out_, out);
+  }
 
-  // The observables with caller-given device buffers for the per-block
+  // The observables, restricted to lo <= coordinate[slab_axis] < hi when
+  // slab_axis >= 0, with caller-given device buffers for the per-block
   // partial sums (obs_partials() doubles) and the kObsN final sums.
-  int observe_into(int axis, int plane, double* part, double* sums, double* out) override {
+  int observe_into(int axis, int plane, int slab_axis, int lo, int hi, double* part, double* sums,
+                   double* out) override {
     P_.flux_axis = axis;
     P_.flux_plane = plane;
+    P_.slab_axis = slab_axis;
+    P_.slab_lo = lo;
+    P_.slab_hi = hi;
     if (dim_ == 3)
       run_obs<3>(part, sums);
     else

@@ -56,7 +56,10 @@ struct EngineBase {
   virtual int n_grid(double* dst) = 0;
   virtual int export_pops(double* fr, double* fb) = 0;
   virtual int observe(int axis, int plane, double* out) = 0;
-  virtual int observe_into(int axis, int plane, double* part, double* sums, double* out) = 0;
+  virtual int observe_into(int axis, int plane, int slab_axis, int lo, int hi, double* part, double* sums,
+                           double* out) = 0;
+  // observables over a slab, with the run's own buffers
+  virtual int observe_slab(int axis, int plane, int slab_axis, int lo, int hi, double* out) = 0;
   // doubles of per-block partial sums that observe_into needs
   virtual size_t obs_partials() const = 0;
   virtual size_t snapshot_bytes() const = 0;

@@ -583,7 +583,20 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
       ok = ok && isfinite((double)u[c]);
       u2 += (double)u[c] * (double)u[c];
     }
-    if (!ok) {
+    const int nxy = P.nx * P.ny;
+    const int cz = v / nxy, cr = v - cz * nxy, cy = cr / P.nx, cx = cr - cy * P.nx;
+    auto coord = [&](int axis) { return axis == 0 ? cx : (axis == 1 ? cy : cz); };
+    // the plane flux over its whole plane, everything else over the slab
+    if (ok && P.flux_axis >= 0 && P.flux_axis < D && coord(P.flux_axis) == P.flux_plane) {
+      const double ua = (double)u[P.flux_axis];
+      o[12] = (a + b) * ua;
+      o[13] = a * ua;
+      o[14] = b * ua;
+    }
+    const bool in_slab =
+        P.slab_axis < 0 || (coord(P.slab_axis) >= P.slab_lo && coord(P.slab_axis) < P.slab_hi);
+    if (!in_slab) {
+    } else if (!ok) {
       o[11] = 1.0;
     } else {
       o[0] = a;
@@ -602,17 +615,6 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
         o[9] = 1.0;
       }
       o[10] = sqrt(u2);
-      if (P.flux_axis >= 0 && P.flux_axis < D) {
-        const int nxy = P.nx * P.ny;
-        const int z = v / nxy, r = v - z * nxy, y = r / P.nx, x = r - y * P.nx;
-        const int c = P.flux_axis == 0 ? x : (P.flux_axis == 1 ? y : z);
-        if (c == P.flux_plane) {
-          const double ua = (double)u[P.flux_axis];
-          o[12] = (a + b) * ua;
-          o[13] = a * ua;
-          o[14] = b * ua;
-        }
-      }
     }
   }
 }

@@ -66,7 +66,7 @@ extern "C" cg_status cg_lbm_observe_noalloc(cg_lbm* h, int axis, int plane, cg_o
   cg_status rc = scratch_ptr(h->device, &base);
   if (rc != CG_OK) return rc;
   double o[cg::kObsN];
-  const int erc = h->eng->observe_into(axis, plane, base + cg::kObsN, base, o);
+  const int erc = h->eng->observe_into(axis, plane, -1, 0, 0, base + cg::kObsN, base, o);
   if (erc != CG_OK)
     return cg::set_error((cg_status)erc, h->eng->err_.empty() ? std::string("device engine error") : h->eng->err_);
   if (cg::fill_observables(o, h->eng->t, out) > 0)

@@ -72,6 +72,8 @@ struct StepParams {
   double rho_in, rho_out, phi_in, zeta_r;
   double eps_c, eps_f, eps_v;
   int flux_axis, flux_plane;
+  // observables restricted to lo <= coordinate[slab_axis] < hi (axis < 0: all)
+  int slab_axis, slab_lo, slab_hi;
 };
 
 template <class Real>

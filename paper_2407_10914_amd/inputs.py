@@ -106,6 +106,22 @@ def tube(nx=24, ny=24, nz=400, radius=10.0, wet_len=40, periodic_z=False) -> Cas
                 dict(kind="tube", radius=radius, wet_len=wet_len))
 
 
+def sessile_box(nx, ny, nz, radius) -> Case:
+    """Channel with solid planes y = 0 and y = ny-1, periodic in x and z, a red
+    hemisphere of the given radius on the floor at the centre of the x-z
+    plane, blue elsewhere (static contact-angle setup of Sec. III.B, whose
+    domain is 102 lattice points between the plates and 201 x 201 along
+    them)."""
+    zz, yy, xx = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, ny - 1, :] = 1
+    cx, cz = nx / 2.0, nz / 2.0
+    red = ((xx - cx) ** 2 + (yy - 0.5) ** 2 + (zz - cz) ** 2 < radius**2) & (yy >= 1) & (yy <= ny - 2)
+    phi = np.where(red, 1.0, -1.0)
+    return Case(solid, phi, (1, 0, 1), 3, dict(kind="sessile_box", radius=radius))
+
+
 def sessile_3d(edge=64, radius=None) -> Case:
     """Cubic box with solid planes y = 0 and y = edge-1, periodic in x and z, a
     red hemisphere of radius 0.25*edge on the floor at the box centre."""

@@ -30,7 +30,8 @@ EXPORTS = ("cg_options_default", "cg_lbm_create", "cg_lbm_destroy", "cg_last_err
            "cg_batch_destroy", "cg_batch_step", "cg_batch_sync", "cg_batch_set_graph", "cg_batch_tune",
            "cg_batch_info", "cg_batch_observe", "cg_lbm_set_wetting", "cg_lbm_set_body_force", "cg_lbm_adjoint",
            "cg_lbm_tune", "cg_lbm_set_pressure", "cg_lbm_switch_inlet", "cg_lbm_line_crossings",
-           "cg_lbm_drop_shape", "cg_batch_graph_captures", "cg_stream_probe", "cg_lbm_observe_noalloc")
+           "cg_lbm_drop_shape", "cg_batch_graph_captures", "cg_stream_probe", "cg_lbm_observe_noalloc",
+           "cg_lbm_observe_slab")
 
 OBJECTIVES = {"saturation": 0, "red_volume": 1, "flux": 2}
 
@@ -144,6 +145,7 @@ def load():
     L.cg_lbm_time.restype = i64
     L.cg_lbm_observe.argtypes = [p, i, i, C.POINTER(Observables)]
     L.cg_lbm_observe_noalloc.argtypes = [p, i, i, C.POINTER(Observables)]
+    L.cg_lbm_observe_slab.argtypes = [p, i, i, i, i, i, C.POINTER(Observables)]
     L.cg_lbm_get_field.argtypes = [p, i, p, i]
     L.cg_lbm_info.argtypes = [p, C.POINTER(Info)]
     L.cg_lbm_snapshot_bytes.argtypes = [p]

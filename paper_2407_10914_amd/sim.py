@@ -138,9 +138,15 @@ class Sim:
     def sync(self):
         L.check(L.load().cg_lbm_sync(self._h))
 
-    def observe(self, axis=-1, plane=0, check=True):
+    def observe(self, axis=-1, plane=0, check=True, slab=None):
+        """Observables; slab = (axis, lo, hi) restricts them (not the plane
+        flux) to the fluid nodes with lo <= coordinate < hi."""
         o = L.Observables()
-        rc = L.load().cg_lbm_observe(self._h, axis, plane, C.byref(o))
+        if slab is None:
+            rc = L.load().cg_lbm_observe(self._h, axis, plane, C.byref(o))
+        else:
+            rc = L.load().cg_lbm_observe_slab(self._h, int(slab[0]), int(slab[1]), int(slab[2]), axis, plane,
+                                              C.byref(o))
         if check:
             L.check(rc)
         return o.as_dict()

@@ -3,7 +3,9 @@
 The oracle differentiates the same n steps in forward mode on dual numbers;
 the GPU runs the reverse kernels.  For a direction d in parameter space the
 two must agree: <grad J, d> (GPU) = dJ[d] (oracle).  FP64 agrees to rounding;
-FP32 to the tolerance derived in the design notes."""
+FP32 to 1e-4 relative (the bound on gradients against finite differences).
+The workload size itself (128^3 drainage rock, 2000 steps) is in
+test_adjoint_scale_gpu.py."""
 import numpy as np
 import pytest
 
@@ -133,7 +135,7 @@ def test_fp32_3d_matches_oracle_tangent(scheme):
     print(f"fp32 scheme {scheme}: J {r['J']:.9e}/{J_t:.9e} dtheta {r['dJ_dtheta']:.6e}/{d_theta:.6e} "
           f"dgz {r['dJ_dg'][2]:.6e}/{d_gz:.6e} rel {e}", flush=True)
     assert e[0] <= 1e-6
-    assert e[1] <= 2e-3 and e[2] <= 2e-3
+    assert e[1] <= 1e-4 and e[2] <= 1e-4
 
 
 def test_autograd_function_hands_out_the_adjoint_gradient():
