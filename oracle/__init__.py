@@ -90,6 +90,7 @@ def lib():
         L.orc_set_threads.argtypes = [i]
         L.orc_set_pressure.argtypes = [p, d, d]
         L.orc_set_body_force.argtypes = [p, p]
+        L.orc_set_visit_order.argtypes = [p, p]
     return _LIB
 
 
@@ -292,6 +293,14 @@ class OracleSim:
     def switch_inlet(self, zeta_r):
         """Replace the injected fluid (Eqs. 37-38): 1.0 = red, 0.0 = blue."""
         _check(lib().orc_switch_inlet(self._h, float(zeta_r)))
+
+    def set_visit_order(self, perm):
+        """Visit the voxels in the order `perm` (a permutation of the flat
+        voxel indices) in every per-voxel loop of the step."""
+        perm = np.ascontiguousarray(perm, dtype=np.int64).ravel()
+        if perm.size != self._solid.size:
+            raise ValueError("perm must list every voxel once")
+        _check(lib().orc_set_visit_order(self._h, _ptr(perm)))
 
     def set_pressure(self, rho_in, rho_out):
         _check(lib().orc_set_pressure(self._h, float(rho_in), float(rho_out)))

@@ -445,6 +445,11 @@ struct Sim {
   std::vector<R> fr, fb, pr, pb;        /* state [Q][V] and post-collision */
   std::vector<R> rr, rb, rho, phi, kap; /* [V] */
   std::vector<R> cvec, nvec, frc, uvel; /* [3][V] */
+  /* Order in which the per-voxel loops of a step visit the voxels (and the
+   * face loops the (x, y) positions): the identity unless a caller sets a
+   * permutation.  Every stage reads only what an earlier stage wrote, so the
+   * order changes no result; a test runs both. */
+  std::vector<long> visit, plane_visit;
 
   long idx(long x, long y, long z) const { return x + nx * (y + ny * z); }
   void coords(long v, long* c) const {
@@ -539,6 +544,10 @@ struct Sim {
       return fail("theta must lie in (0,180)");
     V = nx * ny * nz;
     solid.assign(sol, sol + V);
+    visit.resize(V);
+    for (long v = 0; v < V; ++v) visit[v] = v;
+    plane_visit.resize(nx * ny);
+    for (long k = 0; k < nx * ny; ++k) plane_visit[k] = k;
     long nfl = 0;
     for (long v = 0; v < V; ++v) nfl += fluid(v);
     if (nfl == 0) return fail("no fluid voxel");
@@ -733,6 +742,22 @@ struct Sim {
     return 0;
   }
 
+  /* Visiting order of the step's loops: perm is a permutation of the V voxel
+   * indices; the face loops take the (x, y) positions in the order in which
+   * perm lists the voxels of the plane z = 0. */
+  int set_visit_order(const int64_t* perm) {
+    std::vector<uint8_t> seen(V, 0);
+    for (long k = 0; k < V; ++k) {
+      if (perm[k] < 0 || perm[k] >= V || seen[perm[k]]) return fail("not a permutation of the voxels");
+      seen[perm[k]] = 1;
+    }
+    visit.assign(perm, perm + V);
+    long j = 0;
+    for (long k = 0; k < V; ++k)
+      if (visit[k] < nx * ny) plane_visit[j++] = visit[k];
+    return 0;
+  }
+
   /* New Zou-He densities (Appendix B) for the next steps. */
   int set_pressure(double rho_in, double rho_out) {
     if (p.bc != 1) return fail("inlet/outlet densities need Zou-He faces");
@@ -748,7 +773,8 @@ struct Sim {
     const R phi_in = p.zeta_r - (1.0 - p.zeta_r);
     /* S1: Eqs. (7)-(9) */
 #pragma omp parallel for schedule(static)
-    for (long v = 0; v < V; ++v) {
+    for (long k = 0; k < V; ++k) {
+      const long v = visit[k];
       if (!fluid(v)) continue;
       R a = 0.0, b = 0.0;
       for (int i = 0; i < Q; ++i) a += fr[(size_t)i * V + v];
@@ -761,8 +787,8 @@ struct Sim {
     if (p.bc == 1) {
       /* injected fluid at the inlet (Sec. II.D.1): phi(x_in) = zeta^r - zeta^b;
        * zero-gradient phase field at the outlet, Eq. (39) */
-      for (long y = 0; y < ny; ++y)
-        for (long x = 0; x < nx; ++x) {
+      for (long k = 0; k < nx * ny; ++k) {
+          const long x = plane_visit[k] % nx, y = plane_visit[k] / nx;
           long vi = idx(x, y, 0);
           if (fluid(vi)) phi[vi] = phi_in;
           long vo = idx(x, y, nz - 1);
@@ -775,7 +801,8 @@ struct Sim {
      * reading: Eq. (24) sets phi(x_s) = cos(theta) with theta measured through
      * the red fluid; the angle here is measured through fluid b, as for the
      * other schemes, so phi(x_s) = cos(180 deg - theta) = -cos(theta). */
-    for (long s = 0; s < V; ++s) {
+    for (long k = 0; k < V; ++k) {
+      const long s = visit[k];
       if (!is_sb[s]) continue;
       if (p.scheme == 3) {
         const R th = has_field ? theta_vox_r[s] : theta_global;
@@ -794,7 +821,8 @@ struct Sim {
     }
     /* S3: colour gradient, Eq. (6), and its unit vector, Eq. (27) */
 #pragma omp parallel for schedule(static)
-    for (long v = 0; v < V; ++v) {
+    for (long k = 0; k < V; ++k) {
+      const long v = visit[k];
       if (!fluid(v)) continue;
       R C[3] = {0.0, 0.0, 0.0};
       for (int a = 0; a < D; ++a) {
@@ -823,7 +851,8 @@ struct Sim {
     }
     /* S5: zero-interfacial-force extrapolation of n_c to the solid boundary
      * points, Eq. (35); not renormalised */
-    for (long s = 0; s < V; ++s) {
+    for (long k = 0; k < V; ++k) {
+      const long s = visit[k];
       if (!is_sb[s]) continue;
       R num[3] = {0.0, 0.0, 0.0};
       double den = 0.0;
@@ -838,7 +867,8 @@ struct Sim {
     /* S6-S8: curvature, Eq. (12); CSF force, Eq. (5) plus the body force of
      * Eq. (36) as force density rho_o g; velocity, Eq. (22) */
 #pragma omp parallel for schedule(static)
-    for (long v = 0; v < V; ++v) {
+    for (long k = 0; k < V; ++k) {
+      const long v = visit[k];
       if (!fluid(v)) continue;
       R d[3][3];  /* d[b][a] = d n_a / d x_b, same isotropic stencil as Eq. (6) */
       for (int b = 0; b < 3; ++b)
@@ -877,7 +907,8 @@ struct Sim {
   void step() {
     macro();
 #pragma omp parallel for schedule(static)
-    for (long v = 0; v < V; ++v) {
+    for (long k = 0; k < V; ++k) {
+      const long v = visit[k];
       if (!fluid(v)) continue;
       R ft[19], out[19], cr[19], cb[19];
       for (int i = 0; i < Q; ++i) ft[i] = fr[(size_t)i * V + v] + fb[(size_t)i * V + v];
@@ -902,7 +933,8 @@ struct Sim {
     /* S11: pull streaming, Eq. (1); halfway bounce-back at solid links (P: no-slip
      * bounce-back; reading: halfway placement) */
 #pragma omp parallel for schedule(static)
-    for (long v = 0; v < V; ++v) {
+    for (long k = 0; k < V; ++k) {
+      const long v = visit[k];
       if (!fluid(v)) continue;
       for (int i = 0; i < Q; ++i) {
         long src = link(v, L.opp[i]); /* x - e_i */
@@ -924,8 +956,8 @@ struct Sim {
     /* S12: Zou-He faces (Appendix B) right after streaming */
     if (p.bc == 1) {
       const double zr = p.zeta_r, zb = 1.0 - p.zeta_r;
-      for (long y = 0; y < ny; ++y)
-        for (long x = 0; x < nx; ++x) {
+      for (long k = 0; k < nx * ny; ++k) {
+          const long x = plane_visit[k] % nx, y = plane_visit[k] / nx;
           long vi = idx(x, y, 0);
           if (fluid(vi)) {
             R a[19], b[19];
@@ -1171,6 +1203,10 @@ int orc_switch_inlet(orc_sim* s, double zeta_r_new) {
   return s->s.switch_inlet(zeta_r_new);
 }
 
+int orc_set_visit_order(orc_sim* s, const int64_t* perm) {
+  if (!s || !perm) return fail("null argument");
+  return s->s.set_visit_order(perm);
+}
 int orc_set_pressure(orc_sim* s, double rho_in, double rho_out) {
   if (!s) return fail("null argument");
   return s->s.set_pressure(rho_in, rho_out);

@@ -75,6 +75,12 @@ int orc_switch_inlet(orc_sim* s, double zeta_r_new);
 /* OpenMP threads of the node loops (n > 0 sets them); returns the count in use.
  * Results do not depend on it: no loop reduces across nodes. */
 int orc_set_threads(int n);
+/* Order in which the step's per-voxel loops visit the voxels: perm holds a
+ * permutation of the V voxel indices (x fastest); the face loops follow the
+ * order of the z = 0 voxels in it.  Results do not depend on it (each stage
+ * reads only earlier stages' outputs); it exists so that a test can show
+ * that.  Returns -1 unless perm is a permutation. */
+int orc_set_visit_order(orc_sim* s, const int64_t* perm);
 /* New Zou-He inlet/outlet densities for the following steps. */
 int orc_set_pressure(orc_sim* s, double rho_in, double rho_out);
 /* New body-force acceleration g (Eq. 36) for the following steps. */

@@ -400,6 +400,12 @@ int build_setup(const cg_geometry& g, const cg_wetting& wet, const cg_bc& bc, Ho
 int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
                    std::vector<double>* sin_t, std::vector<unsigned>* flags, std::vector<double>* sb_fd,
                    std::string* err) {
+  const size_t np = (size_t)S.Np;
+  if (!cos_t || !sin_t || !flags || !sb_fd || cos_t->size() != np || sin_t->size() != np || flags->size() != np ||
+      sb_fd->size() != S.sb_vox.size()) {
+    *err = "contact_angles: output arrays must hold one entry per padded node (and per solid boundary point)";
+    return CG_EINVAL;
+  }
   const double deg = M_PI / 180.0;
   // Eq. (24) with the angle measured through fluid b: the fixed phase of a
   // solid boundary point is cos(180 deg - theta) = -cos(theta)

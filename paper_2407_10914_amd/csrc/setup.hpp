@@ -48,7 +48,8 @@ struct HostSetup {
 // per-voxel field (w_i-weighted mean over the solid link neighbours): fills
 // cos_t, sin_t and the FL_S1POS bit of flags for those nodes ([Np] each),
 // and the fictitious-density phase of every solid boundary point from its
-// own angle (sb_fd, [nsb]).  Returns CG_OK or CG_EINVAL with *err set.
+// own angle (sb_fd, [nsb]).  The arrays must have those sizes already.
+// Returns CG_OK or CG_EINVAL with *err set.
 int contact_angles(const HostSetup& S, double theta_deg, const double* theta_field_deg, std::vector<double>* cos_t,
                    std::vector<double>* sin_t, std::vector<unsigned>* flags, std::vector<double>* sb_fd,
                    std::string* err);
