@@ -273,7 +273,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   }
   const CT rho_u = kDev ? rho0 + drho : rho;
   const Vec4<Real> f4 = R.f[n];
-  const Vec4<Real> n4 = R.n[v];
+  const Vec4<Real> n4 = n_get(R.n, v);
   const CT F[3] = {(CT)f4.x, (CT)f4.y, (CT)f4.z};
   const CT kap = (CT)f4.w;
   const CT nv[3] = {(CT)n4.x, (CT)n4.y, (CT)n4.z};
@@ -658,7 +658,7 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
   [[maybe_unused]] __amdgpu_buffer_rsrc_t rn, rk;
   if constexpr (kSb) {
     msk = G.sb_mask[idx];
-    rn = grid_rsrc(R.n, sizeof(Vec4<Real>) * (size_t)P.V);
+    rn = grid_rsrc(R.n, sizeof(Norm3<Real>) * (size_t)P.V);
     rk = grid_rsrc(A.lk, sizeof(Real) * (size_t)P.V);
   }
   unroll<Q - 1>([&](auto J) {
@@ -669,10 +669,10 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
     CT lk;
     if constexpr (kSb) {
       const bool on = msk & (1u << j);
-      q = bload3<Real>(rn, on ? (uint32_t)x * (uint32_t)sizeof(Vec4<Real>) : kOffNone);
+      q = bload3<Real>(rn, on ? (uint32_t)x * (uint32_t)sizeof(Norm3<Real>) : kOffNone);
       lk = bload1(rk, on ? (uint32_t)x * (uint32_t)sizeof(Real) : kOffNone, Real(0));
     } else {
-      q = R.n[x];
+      q = n_get(R.n, x);
       lk = (CT)A.lk[x];
     }
     const CT nq[3] = {(CT)q.x, (CT)q.y, (CT)q.z};
@@ -704,7 +704,7 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
   });
   Vec4<Real> o;
   if constexpr (!kSb) {
-    const Vec4<Real> s4 = R.n[v];
+    const Vec4<Real> s4 = n_get(R.n, v);
     const CT ns[3] = {(CT)s4.x, (CT)s4.y, (CT)s4.z};
     const CT lk = (CT)A.lk[v];
 #pragma unroll

@@ -213,7 +213,7 @@ class AdjointRun {
       const size_t m0 = mem_.size(), b0 = bytes_;
       for (auto& x : g) {
         x.phi = (typename Grids<Real>::PhiT*)get(sizeof(typename Grids<Real>::PhiT) * V);
-        x.n = (V4*)get(sizeof(V4) * V);
+        x.n = (Norm3<Real>*)get(sizeof(Norm3<Real>) * V);
         x.c = (V4*)get(sizeof(V4) * Np);
         x.f = (V4*)get(sizeof(V4) * Np);
         gok = gok && x.phi && x.n && x.c && x.f;
@@ -267,7 +267,7 @@ class AdjointRun {
     // grid voxels that no stage writes (interior solid) are read as zeros
     for (auto& x : fg_) {
       if (e == hipSuccess) e = Engine<Real>::fill_phi_zero(x.phi, V, st);
-      zero(x.n, sizeof(V4) * V);
+      zero(x.n, sizeof(Norm3<Real>) * V);
     }
     if (e != hipSuccess) {
       E.err_ = hipGetErrorString(e);

@@ -47,7 +47,7 @@ class Engine final : public EngineBase {
 
   int init(const HostSetup& S, const StepParams& P, int block, Alloc* al, hipStream_t st,
            std::string* err) override {
-    if ((double)sizeof(V4) * (double)S.V > 4294967040.0) {
+    if ((double)sizeof(V4) * (double)S.V > 4294967040.0) {  // the widest dense grid (adjoint fields)
       *err = "voxel grid too large for 32-bit offsets in this precision";
       return CG_EUNSUPPORTED;
     }
@@ -111,7 +111,7 @@ class Engine final : public EngineBase {
     Real* sbfd = (Real*)dev(sizeof(Real) * (nsb ? nsb : 1));
     using PhiT = typename Grids<Real>::PhiT;
     PhiT* phi = (PhiT*)dev(sizeof(PhiT) * V);
-    V4* ng = (V4*)dev(sizeof(V4) * V);
+    Norm3<Real>* ng = (Norm3<Real>*)dev(sizeof(Norm3<Real>) * V);
     V4* cv = (V4*)dev(sizeof(V4) * Np);
     V4* fv = (V4*)dev(sizeof(V4) * Np);
     const int nb = (S.N + BS - 1) / BS;
@@ -170,7 +170,7 @@ class Engine final : public EngineBase {
     up(sbfd, fdr.data(), sizeof(Real) * nsb);
     // voxels that no stage writes (interior solid) hold phi = 0
     if (e == hipSuccess) e = fill_phi_zero(phi, V, nullptr);
-    if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(V4) * V);
+    if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(Norm3<Real>) * V);
     if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(V4) * Np);
     if (e == hipSuccess) e = hipMemset(fv, 0, sizeof(V4) * Np);
     if (e != hipSuccess) {
@@ -277,7 +277,7 @@ class Engine final : public EngineBase {
       front<3>(4);
     else
       front<2>(4);
-    launch(-1, k_grid_copy4<Real>, P_.V, P_.V, (const V4*)R_.n, dst);
+    launch(-1, k_grid_copy3<Real>, P_.V, P_.V, (const Norm3<Real>*)R_.n, dst);
     CG_HIP(hipGetLastError());
     CG_HIP(hipStreamSynchronize(stream_));
     return CG_OK;

@@ -218,7 +218,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   cv.y = (Real)C[1];
   cv.z = (Real)C[2];
   cv.w = Real(0);
-  R.n[v] = nv;
+  n_put(R.n, v, nv);
   R.c[n] = cv;
 }
 
@@ -239,12 +239,12 @@ __device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, 
   const Pos ps = make_pos(P, v, m & 1u);
   int nbi[Q];
   nb_all<D>(P, ps, nbi);
-  const auto rs = grid_rsrc(R.n, sizeof(Vec4<Real>) * (size_t)P.V);
+  const auto rs = grid_rsrc(R.n, sizeof(Norm3<Real>) * (size_t)P.V);
   Vec4<Real> q[Q];
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
     const bool on = m & (1u << i);
-    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(Vec4<Real>) : kOffNone;
+    const uint32_t off = on ? (uint32_t)nbi[i] * (uint32_t)sizeof(Norm3<Real>) : kOffNone;
     q[i] = bload3<Real>(rs, off);
   });
   Real num[3] = {Real(0), Real(0), Real(0)};
@@ -263,7 +263,7 @@ __device__ __forceinline__ void d_sb_n(const StepParams& P, const Geo<Real>& G, 
   o.y = num[1] / den;
   o.z = D == 3 ? num[2] / den : Real(0);
   o.w = Real(0);
-  R.n[v] = o;
+  n_put(R.n, v, o);
 }
 
 template <class Real, int D>
@@ -292,7 +292,7 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
   Vec4<Real> nb[Q];
   unroll<Q>([&](auto I) {
     constexpr int i = I;
-    if constexpr (i > 0) nb[i] = R.n[nbi[i]];
+    if constexpr (i > 0) nb[i] = n_get(R.n, nbi[i]);
   });
   CT d[3][3];
   unroll<D>([&](auto B_) {
@@ -340,7 +340,7 @@ __device__ __forceinline__ void d_curv(const StepParams& P, const Geo<Real>& G, 
   const int v = vox_of(vf);
   const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
   double F[3], k;
-  curv_force<Real, D>(P, R, n, v, ps, R.n[v], F, k);
+  curv_force<Real, D>(P, R, n, v, ps, n_get(R.n, v), F, k);
   Vec4<Real> o;
   o.x = (Real)F[0];
   o.y = (Real)F[1];
@@ -437,7 +437,7 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   else
     phi = (rr - rb) / rho;
   if (fl & (FL_IN | FL_OUT)) phi = (VT)phi_dec(R.phi[v]);
-  const Vec4<Real> n4 = R.n[v];
+  const Vec4<Real> n4 = n_get(R.n, v);
   // curvature and force of this node (what k_curv stores), in the arithmetic
   // of the mode
   double Fd[3], kd;
@@ -828,12 +828,12 @@ __global__ void k_grid_copy(int count, const T* grid, double* dst) {
   dst[n] = phi_dec(grid[n]);
 }
 
-// Dense voxel grid of 4-vectors -> dense FP64 [3][V] array.
+// Dense voxel grid of normals -> dense FP64 [3][V] array.
 template <class Real>
-__global__ void k_grid_copy4(int count, const Vec4<Real>* grid, double* dst) {
+__global__ void k_grid_copy3(int count, const Norm3<Real>* grid, double* dst) {
   const int n = node_id();
   if (n >= count) return;
-  const Vec4<Real> q = grid[n];
+  const Vec4<Real> q = n_get(grid, n);
   dst[n] = (double)q.x;
   dst[(size_t)count + n] = (double)q.y;
   dst[2 * (size_t)count + n] = (double)q.z;

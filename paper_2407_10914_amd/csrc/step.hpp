@@ -89,6 +89,28 @@ struct Vec4T<double> {
 template <class Real>
 using Vec4 = typename Vec4T<Real>::type;
 
+// Interface normal as the dense grid stores it: three components and no
+// padding, so that a stencil gather of a wave touches a quarter fewer cache
+// lines than with 16-byte vectors.
+template <class Real>
+struct Norm3 {
+  Real x, y, z;
+};
+template <class Real>
+__device__ __forceinline__ Vec4<Real> n_get(const Norm3<Real>* p, int i) {
+  const Norm3<Real> t = p[i];
+  Vec4<Real> o;
+  o.x = t.x;
+  o.y = t.y;
+  o.z = t.z;
+  o.w = Real(0);
+  return o;
+}
+template <class Real>
+__device__ __forceinline__ void n_put(Norm3<Real>* p, int i, const Vec4<Real>& v) {
+  p[i] = Norm3<Real>{v.x, v.y, v.z};
+}
+
 // Pull table: the source node of direction i (i >= 1) of node n, or a code.
 // Stored as 16-bit deltas against a per-tile base (a tile is 256 consecutive
 // nodes; every wave lies inside one tile): s = n + base[i][tile] + d, with two
@@ -249,7 +271,7 @@ template <class Real>
 struct Grids {
   using PhiT = typename PhiStore<Real>::type;
   PhiT* phi;        // [V] phase field (fluid nodes and solid boundary points), see PhiStore
-  Vec4<Real>* n;    // [V] interface normal after wetting (xyz), fluid and S_b
+  Norm3<Real>* n;   // [V] interface normal after wetting, fluid and S_b
   Vec4<Real>* c;    // [Np] colour gradient after wetting (xyz)
   Vec4<Real>* f;    // [Np] force (xyz) and curvature (w)
 };
