@@ -269,9 +269,11 @@ cg_status cg_lbm_load(cg_lbm* h, const void* src);
 /* Kernel timing: mask selects the kernels whose every launch is bracketed by
  * HIP events on the handle's stream (bit k = k-th kernel in the order
  * cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n, k_curv,
- * k_main; -1 = all, 0 = off).  A time step runs k_phase, k_sb_phi, k_normal,
- * k_sb_n and k_main (which evaluates the curvature and force of its node);
- * k_curv stores them for the reverse steps of the adjoint.
+ * k_main, k_face; -1 = all, 0 = off).  A time step runs k_phase, k_sb_phi,
+ * k_normal, k_sb_n and k_main (which evaluates the curvature and force of its
+ * node); a single-precision run with Zou-He faces also runs k_face (the
+ * faces' unknowns at the face nodes) after k_phase; k_curv stores the
+ * curvature and force for the reverse steps of the adjoint.
  * cg_lbm_kernel_times synchronises, then reports for each kernel its name,
  * launch count and total milliseconds since the last reset (n: in =
  * capacity, out = count). */
@@ -446,9 +448,9 @@ cg_status cg_batch_set_graph(cg_batch* b, int on);
  * first when a run's state was just set.  report (may be NULL) receives a
  * summary. */
 cg_status cg_batch_tune(cg_batch* b, int reps, char* report, size_t report_len);
-/* total fluid nodes; chosen block and grid per stage (5 entries each, stages
- * in step order: phase, sb_phi, normal, sb_n, main; grid 0 = one block per
- * tile) */
+/* total fluid nodes; chosen block and grid per stage (6 entries each, stages
+ * in step order: phase, face (the Zou-He face nodes of single-precision
+ * runs), sb_phi, normal, sb_n, main; grid 0 = one block per tile) */
 cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int* grid);
 /* Number of step graphs the batch has captured: one per starting ping-pong
  * parity, so at most 2 until the configuration changes (cg_batch_tune,

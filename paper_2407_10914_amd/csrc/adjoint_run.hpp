@@ -99,7 +99,7 @@ class AdjointRun {
   template <int D>
   auto in_of(const Slot& s) const {
     if constexpr (kF32)
-      return InCompact<D>{(const float*)s.a, (const float4*)s.b, E.P_.Np, (float)E.P_.rho0};
+      return InCompact<D>{(const float*)s.a, (const float4*)s.b, E.P_.Np, (float)E.P_.rho0, E.rs_, E.fs_};
     else
       return InCanon<Real, D>{(const Real*)s.a, (const Real*)s.b, E.P_.Np};
   }

@@ -48,8 +48,8 @@ struct RunDesc {
 
 // Stages of one step (the main stage evaluates the curvature and force of its
 // node itself).
-enum { ST_PHASE = 0, ST_SB_PHI, ST_NORMAL, ST_SB_N, ST_MAIN, ST_COUNT };
-static const char* const kStageNames[ST_COUNT] = {"phase", "sb_phi", "normal", "sb_n", "main"};
+enum { ST_PHASE = 0, ST_FACE, ST_SB_PHI, ST_NORMAL, ST_SB_N, ST_MAIN, ST_COUNT };
+static const char* const kStageNames[ST_COUNT] = {"phase", "face", "sb_phi", "normal", "sb_n", "main"};
 constexpr bool stage_on_sb(int st) { return st == ST_SB_PHI || st == ST_SB_N; }
 
 template <class Real, int D, int BS, int St>
@@ -64,6 +64,9 @@ __global__ void __launch_bounds__(BS) kb_stage(const RunDesc<Real, D>* __restric
     const int n = tl.y + (int)threadIdx.x;
     if constexpr (St == ST_PHASE) {
       d_phase<Real, D>(d.P, d.G, d.R, d.in, n);
+    } else if constexpr (St == ST_FACE) {
+      // the node tiles of every run; only the Zou-He face nodes do work
+      if (n < d.P.n_in || (n >= d.P.N - d.P.n_out && n < d.P.N)) d_face<Real, D>(d.P, d.G, d.R, d.in, n);
     } else if constexpr (St == ST_SB_PHI) {
       d_sb_phi<Real, D>(d.P, d.G, d.R, n);
     } else if constexpr (St == ST_NORMAL) {
@@ -300,6 +303,7 @@ class Batch final : public BatchBase {
   std::string arch_;
   void* descs_[2] = {nullptr, nullptr};
   StageCfg cfg_[ST_COUNT];
+  bool any_face_ = false;
   // tile tables per (node/sb, block size)
   std::map<std::pair<int, int>, std::pair<int2*, int>> tiles_;
   bool use_graph_ = true;
@@ -343,6 +347,8 @@ class Batch final : public BatchBase {
         const int c = e->cur() ^ q;
         h[r] = RunDesc<Real, D>{e->params(), e->geo(), e->grids(), e->template in_at<D>(c),
                                 e->template out_at<D>(c)};
+        // single-precision runs with Zou-He faces need the face stage
+        if (sizeof(Real) == 4 && e->params().n_in + e->params().n_out > 0) any_face_ = true;
       }
       if (hipMemcpy(descs_[q], h.data(), sizeof(RunDesc<Real, D>) * h.size(), hipMemcpyHostToDevice) !=
           hipSuccess)
@@ -398,6 +404,10 @@ class Batch final : public BatchBase {
     switch (st) {
       case ST_PHASE:
         hipLaunchKernelGGL((kb_stage<Real, D, BS, ST_PHASE>), dim3(g), dim3(BS), 0, stream_, d, tl.first, ntiles, per);
+        break;
+      case ST_FACE:
+        if (!any_face_) break;
+        hipLaunchKernelGGL((kb_stage<Real, D, BS, ST_FACE>), dim3(g), dim3(BS), 0, stream_, d, tl.first, ntiles, per);
         break;
       case ST_SB_PHI:
         hipLaunchKernelGGL((kb_stage<Real, D, BS, ST_SB_PHI>), dim3(g), dim3(BS), 0, stream_, d, tl.first, ntiles,

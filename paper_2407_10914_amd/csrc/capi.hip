@@ -122,6 +122,8 @@ cg_status cg_lbm_create(const cg_geometry* geom, double tau_r, double tau_b, dou
   P.V = S.V;
   for (int a = 0; a < 3; ++a) P.per[a] = S.per[a];
   P.bc = b.type;
+  P.n_in = b.type == CG_BC_ZOUHE ? S.n_in : 0;
+  P.n_out = b.type == CG_BC_ZOUHE ? S.n_out : 0;
   P.scheme = w.scheme;
   P.collision = o.collision;
   P.half_sigma = 0.5 * sigma;
@@ -549,7 +551,7 @@ cg_status cg_batch_info(const cg_batch* b, int64_t* total_nodes, int* block, int
   if (total_nodes) *total_nodes = b->impl->total_nodes();
   int bs[8], gr[8];
   b->impl->get_config(bs, gr);
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < 6; ++k) {
     if (block) block[k] = bs[k];
     if (grid) grid[k] = gr[k];
   }

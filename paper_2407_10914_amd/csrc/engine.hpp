@@ -61,6 +61,17 @@ class Engine final : public EngineBase {
     al_ = al;
     stream_ = st;
     P_ = P;
+    // the phase stage hands the step kernel the face nodes' values by their
+    // rank among the face nodes, which needs the inlet nodes first and the
+    // outlet nodes last (voxel order with z slowest)
+    for (int n = 0; n < S.N; ++n) {
+      const unsigned f = S.flags[n] & (FL_IN | FL_OUT);
+      const unsigned want = n < P.n_in ? FL_IN : (n >= S.N - P.n_out ? FL_OUT : 0u);
+      if (f != want) {
+        *err = "Zou-He face nodes are not the first and last nodes";
+        return CG_EINVAL;
+      }
+    }
     dim_ = S.dim;
     Q_ = S.Q;
     const size_t Np = (size_t)S.Np, V = (size_t)S.V;
@@ -123,6 +134,8 @@ class Engine final : public EngineBase {
         T_[k] = (float*)dev(sizeof(float) * Q * Np);
         AC_[k] = (float4*)dev(sizeof(float4) * Np);
       }
+      rs_ = (double*)dev(sizeof(double) * Np);
+      fs_ = (float*)dev(sizeof(float) * 5 * (size_t)(P.n_in + P.n_out > 0 ? P.n_in + P.n_out : 1));
       pre_r_ = (Real*)dev(sizeof(Real) * Q * Np);
       pre_x_ = (Real*)dev(sizeof(Real) * Q * Np);
       state_bytes_ = sizeof(float) * Q * Np + sizeof(float4) * Np;
@@ -544,7 +557,7 @@ class Engine final : public EngineBase {
   template <int D>
   auto in_at(int c) const {
     if constexpr (kF32)
-      return InCompact<D>{T_[c], AC_[c], P_.Np, (float)P_.rho0};
+      return InCompact<D>{T_[c], AC_[c], P_.Np, (float)P_.rho0, rs_, fs_};
     else
       return InCanon<Real, D>{fr_[c], fb_[c], P_.Np};
   }
@@ -581,12 +594,15 @@ class Engine final : public EngineBase {
   Alloc* al_ = nullptr;
   hipStream_t stream_ = nullptr;
   int dim_ = 3, Q_ = 19, nsb_ = 0, cur_ = 0;
-  int bs_[K_COUNT] = {256, 256, 256, 256, 256, 256};
+  static_assert(K_COUNT == 7, "one default block size per kernel");
+  int bs_[K_COUNT] = {256, 256, 256, 256, 256, 256, 256};
   bool pre_ = true;
   Real* fr_[2] = {nullptr, nullptr};
   Real* fb_[2] = {nullptr, nullptr};
   float* T_[2] = {nullptr, nullptr};
   float4* AC_[2] = {nullptr, nullptr};
+  double* rs_ = nullptr;  // phase stage -> step kernel: red density pulled in (FP32)
+  float* fs_ = nullptr;   // phase stage -> step kernel: Zou-He unknowns of the face nodes
   Real* pre_r_ = nullptr;
   Real* pre_x_ = nullptr;
   double* obs_part_ = nullptr;
@@ -669,7 +685,7 @@ class Engine final : public EngineBase {
   template <int D>
   auto in_post() const {
     if constexpr (kF32)
-      return InCompact<D>{T_[cur_], AC_[cur_], P_.Np, (float)P_.rho0};
+      return InCompact<D>{T_[cur_], AC_[cur_], P_.Np, (float)P_.rho0, rs_, fs_};
     else
       return InCanon<Real, D>{fr_[cur_], fb_[cur_], P_.Np};
   }
@@ -695,6 +711,9 @@ class Engine final : public EngineBase {
   template <int D, class In>
   void front_with(const In& in, int upto) {
     launch(K_PHASE, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
+    if constexpr (std::is_same_v<In, InCompact<D>>) {
+      if (P_.n_in + P_.n_out > 0) launch(K_FACE, k_face<Real, D, In>, 64 * face_tiles(P_), P_, G_, R_, in);
+    }
     if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
     if (upto >= 3) launch(K_NORMAL, k_normal<Real, D>, P_.N, P_, G_, R_);
     if (upto >= 4 && nsb_) launch(K_SB_N, k_sb_n<Real, D>, nsb_, P_, G_, R_);

@@ -41,8 +41,9 @@ struct Alloc {
 // most interface points one line query returns
 constexpr int kLineMax = 256;
 
-enum { K_PHASE = 0, K_SB_PHI, K_NORMAL, K_SB_N, K_CURV, K_MAIN, K_COUNT };
-static const char* const kKernelNames[K_COUNT] = {"k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main"};
+enum { K_PHASE = 0, K_SB_PHI, K_NORMAL, K_SB_N, K_CURV, K_MAIN, K_FACE, K_COUNT };
+static const char* const kKernelNames[K_COUNT] = {"k_phase", "k_sb_phi", "k_normal", "k_sb_n",
+                                                  "k_curv",  "k_main",   "k_face"};
 
 struct EngineBase {
   virtual ~EngineBase() = default;

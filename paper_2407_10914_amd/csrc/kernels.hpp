@@ -74,8 +74,56 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
       node_moments<D, kDev>(fr, fx, (CT)P.rho0, rr, rb, rho, drho);
     }
     phi = (rr - rb) / rho;
+    if constexpr (std::is_same_v<In, InCompact<D>>) {
+      if (!(fl & FL_OUT)) __builtin_nontemporal_store(rr, &in.RS[n]);
+    }
   }
   R.phi[vox_of(vf)] = phi_enc<typename Grids<Real>::PhiT>(phi);
+}
+
+// Zou-He face node n of the compact single-precision state (after the phase
+// stage, which stored its phase): its pulled populations with the faces
+// applied, Appendix B, in the step kernel's single-precision arithmetic.  The
+// step kernel takes the red sum and the five unknowns from here.  A kernel of
+// its own, so that the per-colour pull of these few nodes does not set the
+// register count of the phase stage.
+template <class Real, int D, class In>
+__device__ __forceinline__ void d_face(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R, const In& in,
+                                       int n) {
+  if constexpr (std::is_same_v<In, InCompact<D>> && D == 3) {
+    constexpr int Q = Lat<D>::Q;
+    const unsigned vf = ld_once(&G.vf[n]);
+    const unsigned fl = flags_of(vf);
+    float fr[Q], fx[Q];
+    load_node<D>(in, G.nbr, n, fr, fx);
+    zou_he<true>(P, fl, (float)phi_dec(R.phi[vox_of(vf)]), fr, fx);
+    double rs = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) rs = rs + (double)fr[i];
+    in.RS[n] = rs;
+    const int k = face_slot(P, fl, n), nf = P.n_in + P.n_out;
+    const bool fin = fl & FL_IN;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) in.FS[q * nf + k] = fin ? fx[kZhIn[q]] : fx[kZhOut[q]];
+  }
+}
+
+// Wave w of the launch covers one whole tile of 64 nodes (the pull table
+// decodes per tile): first the tiles that hold inlet nodes, then those that
+// hold outlet nodes; lanes on other nodes return.  face_tiles() gives the
+// number of waves.
+__host__ __device__ inline int face_tiles_in(const StepParams& P) { return (P.n_in + 63) >> 6; }
+__host__ __device__ inline int face_tiles(const StepParams& P) {
+  return P.n_out > 0 ? face_tiles_in(P) + ((P.N + 63) >> 6) - ((P.N - P.n_out) >> 6) : face_tiles_in(P);
+}
+template <class Real, int D, class In>
+__global__ void k_face(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
+  const int t = node_id_plain();
+  const int w = t >> 6, lane = t & 63, tin = face_tiles_in(P);
+  if (w >= face_tiles(P)) return;
+  const int n = w < tin ? (w << 6) + lane : ((((P.N - P.n_out) >> 6) + w - tin) << 6) + lane;
+  const bool face = w < tin ? n < P.n_in : (n >= P.N - P.n_out && n < P.N);
+  if (face) d_face<Real, D, In>(P, G, R, in, n);
 }
 
 template <class Real, int D, class In>
@@ -421,13 +469,47 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
   // the step computes in the storage precision; the read-out modes rebuild
   // the pulled populations and evaluate everything in double
   using VT = std::conditional_t<Mode == MODE_STEP, Real, CT>;
+  // the single-precision step pulls the totals g only: the red density
+  // pulled in (and at face nodes the unknowns the faces set) were summed by
+  // the phase stage of this step
+  constexpr bool kSums = Mode == MODE_STEP && std::is_same_v<In, InCompact<D>>;
   VT fr[Q], fx[Q];
-  load_node<D>(in, G.nbr, n, fr, fx);
-  if constexpr (In::kPull) {
-    if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (VT)phi_dec(R.phi[v]), fr, fx);
-  }
   VT rr, rb, rho, drho;
-  node_moments<D, kDev>(fr, fx, (VT)P.rho0, rr, rb, rho, drho);
+  [[maybe_unused]] double rr_in = 0.0;
+  if constexpr (kSums) {
+    load_node_t<D>(in, G.nbr, n, fx);
+    if constexpr (D == 3) {
+      if (fl & (FL_IN | FL_OUT)) {
+        const int k = face_slot(P, fl, n), nf = P.n_in + P.n_out;
+        const bool fin = fl & FL_IN;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const float g = in.FS[q * nf + k];
+          fx[kZhIn[q]] = fin ? g : fx[kZhIn[q]];
+          fx[kZhOut[q]] = fin ? fx[kZhOut[q]] : g;
+        }
+      }
+    }
+    rr_in = __builtin_nontemporal_load(&in.RS[n]);
+    VT b = fx[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) b = b + fx[i];
+    VT t = (VT)Lat<D>::w(0) * (VT)P.rho0 + fx[0];
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      t = t + ((VT)Lat<D>::w(i) * (VT)P.rho0 + fx[i]);
+    });
+    drho = b;
+    rho = t;
+    rr = (VT)rr_in;
+    rb = t - rr;
+  } else {
+    load_node<D>(in, G.nbr, n, fr, fx);
+    if constexpr (In::kPull) {
+      if (D == 3 && (fl & (FL_IN | FL_OUT))) zou_he<kDev>(P, fl, (VT)phi_dec(R.phi[v]), fr, fx);
+    }
+    node_moments<D, kDev>(fr, fx, (VT)P.rho0, rr, rb, rho, drho);
+  }
   // the phase of this node from the densities just pulled (k_phase stored
   // the same value, summed in double); Zou-He nodes keep the stored one,
   // which the boundary condition imposes
@@ -506,18 +588,18 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
     const Real rsum = rr + rb;
     if constexpr (kDev) {
       // a is the red share of every population leaving the node: the red
-      // density pulled in and the post-collision total that the next pull
-      // rebuilds from g'' (single-precision weights, as in InCompact) are
-      // summed in double, and a is their correctly rounded quotient, so the
-      // red mass leaving equals the red mass that arrived up to the rounding
-      // of a (single-precision sums drifted the colour masses by ~1e-9 per
-      // step while interfaces move).  b only scales the segregation term,
-      // whose weights cancel.
+      // density pulled in (summed in double) over the post-collision total
+      // as the next phase stage rebuilds it from g'' (w rho0 + g'' in
+      // double), correctly rounded, so the red mass leaving equals the red
+      // mass that arrived up to the rounding of a (single-precision sums
+      // drifted the colour masses by ~1e-9 per step while interfaces move).
+      // b only scales the segregation term, whose weights cancel.
       double rrd = 0.0, td = 0.0;
+      if constexpr (kSums) rrd = rr_in;
       unroll<Q>([&](auto I) {
         constexpr int i = I;
-        rrd = rrd + (double)fr[i];
-        td = td + ((double)((float)Lat<D>::w(i) * (float)P.rho0) + (double)fx[i]);
+        if constexpr (!kSums) rrd = rrd + (double)fr[i];
+        td = td + ((double)Lat<D>::w(i) * (double)(float)P.rho0 + (double)fx[i]);
       });
       const Real a = (Real)(rrd / td);
       const Real b = rr * rb * __builtin_amdgcn_rcpf(rsum);

@@ -61,6 +61,9 @@ struct StepParams {
   int V;     // voxels
   int per[3];
   int bc;    // 0 none, 1 Zou-He z faces
+  // Zou-He face nodes: in voxel order the inlet plane's nodes come first and
+  // the outlet plane's last, so they are nodes [0, n_in) and [N - n_out, N)
+  int n_in, n_out;
   int scheme;     // 0 none, 1 Scheme-I, 2 Scheme-II, 3 fictitious density (Eq. 24)
   int collision;  // 0 BGK, 1 MRT
   double half_sigma;  // 0.5 * sigma
@@ -406,6 +409,13 @@ struct InCompact {
   const float4* AC;
   int Np;
   float rho0;
+  // Written by the phase stage, read by the step kernel of the same step:
+  // RS[n] = red density pulled into node n, summed in double (after the
+  // Zou-He faces at face nodes); FS[q * (n_in + n_out) + k] = the five
+  // unknown totals g the faces set at face node k (inlet nodes first).  The
+  // step kernel then needs no source's (a, c) record.
+  double* RS;
+  float* FS;
   // The rest population of node n (get<0>) split into its two loads and its
   // arithmetic, so that load_node can issue the loads ahead of the pull table.
   struct Rest {
@@ -480,7 +490,49 @@ struct InCompact {
   __device__ __forceinline__ void get_pull(int s, int n, CT& r, CT& x) const {
     finish_pull<i>(load_pull<i>(s, n), s, r, x);
   }
+  // the total alone (g of direction i as pulled; 0 on an open face)
+  template <int i>
+  __device__ __forceinline__ float load_pull_t(int s, int n) const {
+    constexpr int o = opp<D>(i);
+    const bool fl = s >= 0;
+    int node = fl ? s : n;
+    int row = fl ? i * Np : o * Np;
+    asm("" : "+v"(node), "+v"(row));
+    return T[row + node];
+  }
 };
+
+// Unknown directions of the inlet and of the outlet (Eqs. B.1-B.18): the
+// populations that enter the domain through the face.
+constexpr int kZhIn[5] = {5, 11, 12, 15, 16};
+constexpr int kZhOut[5] = {6, 13, 14, 17, 18};
+
+// Index of a Zou-He face node among the face nodes (inlet ones first).
+__device__ __forceinline__ int face_slot(const StepParams& P, unsigned fl, int n) {
+  return (fl & FL_IN) ? n : P.n_in + (n - (P.N - P.n_out));
+}
+
+// Pulled totals g_i of node n of the compact state (the step kernel's pull:
+// no red share).  Same order of loads as load_node.
+template <int D>
+__device__ __forceinline__ void load_node_t(const InCompact<D>& in, const Nbr& nbr, int n, float* fx) {
+  constexpr int Q = Lat<D>::Q;
+  const float t0 = in.T[n];
+  __builtin_amdgcn_sched_barrier(0);
+  int src[Q];
+  nbr.template all<Q>(n, src);
+  float raw[Q];
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    raw[i] = in.template load_pull_t<i>(src[i], n);
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    fx[i] = src[i] < kBounce ? 0.f : raw[i];
+  });
+  fx[0] = t0;
+}
 
 // Pre-collision populations stored at their own node (first step after the
 // state was set from the host).
@@ -659,14 +711,12 @@ __device__ __forceinline__ void zou_he(const StepParams& P, unsigned fl, CT phi_
     zh_out_color(orr, jt * chr);
     zh_out_color(ox, jt * chb);
   }
-  constexpr int kIn[5] = {5, 11, 12, 15, 16};
-  constexpr int kOut[5] = {6, 13, 14, 17, 18};
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    fr[kIn[q]] = in ? ir[kIn[q]] : fr[kIn[q]];
-    fx[kIn[q]] = in ? ix[kIn[q]] : fx[kIn[q]];
-    fr[kOut[q]] = out ? orr[kOut[q]] : fr[kOut[q]];
-    fx[kOut[q]] = out ? ox[kOut[q]] : fx[kOut[q]];
+    fr[kZhIn[q]] = in ? ir[kZhIn[q]] : fr[kZhIn[q]];
+    fx[kZhIn[q]] = in ? ix[kZhIn[q]] : fx[kZhIn[q]];
+    fr[kZhOut[q]] = out ? orr[kZhOut[q]] : fr[kZhOut[q]];
+    fx[kZhOut[q]] = out ? ox[kZhOut[q]] : fx[kZhOut[q]];
   }
 }
 

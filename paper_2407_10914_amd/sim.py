@@ -256,7 +256,7 @@ class Sim:
                 "work_bytes": gr.work_bytes}
 
     # ---------------------------------------------------------------- timing
-    KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main")
+    KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main", "k_face")
 
     def set_timing(self, kernels="all"):
         """Bracket launches of the named kernels with HIP events ("all", None,
@@ -340,7 +340,7 @@ class Batch:
 
     def info(self):
         n = C.c_int64()
-        bs = (C.c_int * 5)()
-        gr = (C.c_int * 5)()
+        bs = (C.c_int * 6)()
+        gr = (C.c_int * 6)()
         L.check(L.load().cg_batch_info(self._h, C.byref(n), bs, gr))
         return {"total_nodes": n.value, "block": list(bs), "grid": list(gr)}
