@@ -580,7 +580,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   na.w = db;
   A.na[n] = na;
   // force F = sigma/2 kappa C + rho0 g
-  const Vec4<Real> c4 = R.c[n];
+  const Vec4<Real> c4 = n_get(R.c, n);
   const CT Cv[3] = {(CT)c4.x, (CT)c4.y, (CT)c4.z};
   CT lkap = CT(0);
 #pragma unroll

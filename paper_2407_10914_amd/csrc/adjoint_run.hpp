@@ -214,7 +214,7 @@ class AdjointRun {
       for (auto& x : g) {
         x.phi = (typename Grids<Real>::PhiT*)get(sizeof(typename Grids<Real>::PhiT) * V);
         x.n = (Norm3<Real>*)get(sizeof(Norm3<Real>) * V);
-        x.c = (V4*)get(sizeof(V4) * Np);
+        x.c = (Norm3<Real>*)get(sizeof(Norm3<Real>) * Np);
         x.f = (V4*)get(sizeof(V4) * Np);
         gok = gok && x.phi && x.n && x.c && x.f;
         if (!gok) break;

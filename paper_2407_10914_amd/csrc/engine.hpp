@@ -123,7 +123,7 @@ class Engine final : public EngineBase {
     using PhiT = typename Grids<Real>::PhiT;
     PhiT* phi = (PhiT*)dev(sizeof(PhiT) * V);
     Norm3<Real>* ng = (Norm3<Real>*)dev(sizeof(Norm3<Real>) * V);
-    V4* cv = (V4*)dev(sizeof(V4) * Np);
+    Norm3<Real>* cv = (Norm3<Real>*)dev(sizeof(Norm3<Real>) * Np);
     V4* fv = (V4*)dev(sizeof(V4) * Np);
     const int nb = (S.N + BS - 1) / BS;
     obs_part_ = (double*)dev(sizeof(double) * (size_t)kObsN * (nb + 1));
@@ -184,7 +184,7 @@ class Engine final : public EngineBase {
     // voxels that no stage writes (interior solid) hold phi = 0
     if (e == hipSuccess) e = fill_phi_zero(phi, V, nullptr);
     if (e == hipSuccess) e = hipMemset(ng, 0, sizeof(Norm3<Real>) * V);
-    if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(V4) * Np);
+    if (e == hipSuccess) e = hipMemset(cv, 0, sizeof(Norm3<Real>) * Np);
     if (e == hipSuccess) e = hipMemset(fv, 0, sizeof(V4) * Np);
     if (e != hipSuccess) {
       *err = std::string("upload failed: ") + hipGetErrorString(e);

@@ -19,14 +19,12 @@ __device__ __forceinline__ int vox_of(unsigned vf) { return (int)(vf & kVoxMask)
 // several waves reuse, out of L2.
 __device__ __forceinline__ unsigned ld_once(const unsigned* p) { return __builtin_nontemporal_load(p); }
 template <class Real>
-__device__ __forceinline__ Vec4<Real> ld_once4(const Vec4<Real>* p) {
-  typedef Real v4 __attribute__((ext_vector_type(4)));
-  const v4 t = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+__device__ __forceinline__ Vec4<Real> ld_once3(const Norm3<Real>* p) {
   Vec4<Real> o;
-  o.x = t.x;
-  o.y = t.y;
-  o.z = t.z;
-  o.w = t.w;
+  o.x = __builtin_nontemporal_load(&p->x);
+  o.y = __builtin_nontemporal_load(&p->y);
+  o.z = __builtin_nontemporal_load(&p->z);
+  o.w = Real(0);
   return o;
 }
 __device__ __forceinline__ unsigned flags_of(unsigned vf) { return vf >> kVoxBits; }
@@ -267,7 +265,7 @@ __device__ __forceinline__ void d_normal(const StepParams& P, const Geo<Real>& G
   cv.z = (Real)C[2];
   cv.w = Real(0);
   n_put(R.n, v, nv);
-  R.c[n] = cv;
+  n_put(R.c, n, cv);
 }
 
 template <class Real, int D>
@@ -374,7 +372,7 @@ __device__ __forceinline__ void curv_force(const StepParams& P, const Grids<Real
   k = (double)kk;
   // C as stored by k_normal: rebuilding it as |C| n in single precision
   // triples its rounding, which the force passes straight to the velocity
-  const Vec4<Real> c = ld_once4<Real>(&R.c[n]);
+  const Vec4<Real> c = ld_once3<Real>(&R.c[n]);
   const CT C[3] = {(CT)c.x, (CT)c.y, (CT)c.z};
   F[0] = F[1] = F[2] = 0.0;
 #pragma unroll
@@ -644,7 +642,7 @@ __device__ __forceinline__ void d_main(const StepParams& P, const Geo<Real>& G, 
       });
     }
   } else if constexpr (Mode == MODE_MACRO) {
-    const Vec4<Real> c4 = R.c[n];
+    const Vec4<Real> c4 = n_get(R.c, n);
     if (mo.rho_r) mo.rho_r[v] = (double)rr;
     if (mo.rho_b) mo.rho_b[v] = (double)rb;
     if (mo.phi) mo.phi[v] = (double)phi;

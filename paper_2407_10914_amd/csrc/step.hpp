@@ -275,7 +275,7 @@ struct Grids {
   using PhiT = typename PhiStore<Real>::type;
   PhiT* phi;        // [V] phase field (fluid nodes and solid boundary points), see PhiStore
   Norm3<Real>* n;   // [V] interface normal after wetting, fluid and S_b
-  Vec4<Real>* c;    // [Np] colour gradient after wetting (xyz)
+  Norm3<Real>* c;   // [Np] colour gradient after wetting
   Vec4<Real>* f;    // [Np] force (xyz) and curvature (w)
 };
 
