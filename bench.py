@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-k", type=int, default=100)
     ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
+                    help="also run the library's plain 1 GiB copy kernel (reference for the HBM byte counters)")
     ap.add_argument("--windows", type=int, default=5, help="timed windows the --steps are split into (median)")
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the streaming-kernel sweep that measures the HBM ceiling")
@@ -361,12 +361,17 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if args.copy_calib:
+        # the library's own plain copy kernel (k_stream<2, false>) over 1 GiB:
+        # the reference of known size for the HBM byte counters
+        from paper_2407_10914_amd import roofline
+
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        ms = roofline.probe("copy", x, y, 1 << 30, 8 * cus, 256, False, reps=3)
         torch.cuda.synchronize()
-        print("# copy calibration: 3 x 1 GiB device-to-device copies", file=sys.stderr, flush=True)
+        print(f"# copy calibration: 1 GiB copy kernel, {ms:.3f} ms per launch (4 launches)", file=sys.stderr,
+              flush=True)
         del x, y
     f64 = None
     if not args.no_fp64:
