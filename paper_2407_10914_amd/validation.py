@@ -262,7 +262,10 @@ def main(argv=None):
     ap.add_argument("which", choices=("laplace", "angle", "washburn", "all"))
     ap.add_argument("--json", default=None)
     ap.add_argument("--precision", default="f32")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="steps of the Laplace and contact-angle runs (default 10000 and 20000)")
     a = ap.parse_args(argv)
+    extra = {} if a.steps is None else {"steps": a.steps}
     import torch
 
     torch.cuda.set_device(0)
@@ -271,9 +274,9 @@ def main(argv=None):
     for w in (("laplace", "angle", "washburn") if a.which == "all" else (a.which,)):
         t0 = time.perf_counter()
         if w == "laplace":
-            res[w] = laplace_sweep(precision=a.precision, log=log)
+            res[w] = laplace_sweep(precision=a.precision, log=log, **extra)
         elif w == "angle":
-            res[w] = angle_sweep(precision=a.precision, log=log)
+            res[w] = angle_sweep(precision=a.precision, log=log, **extra)
         else:
             res[w] = washburn_runs(precision=a.precision, log=log)
         res[w]["wall_s"] = round(time.perf_counter() - t0, 1)
