@@ -334,6 +334,7 @@ def main():
             "bytes_alg_per_launch": B_ALG_F32_D3Q19 * n_fluid, "avg_launch_us": round(main_avg_s * 1e6, 2),
             "block": main_block}
     step_frac = mlups * 1e6 * B_ALG_F32_D3Q19 / (HBM_PEAK_GBS * 1e9)
+    roof["step_hbm_frac_alg"] = round(step_frac, 4)  # the whole step's algorithmic rate against the peak
     ceiling = None
     if not args.no_ceiling:
         from paper_2407_10914_amd import roofline

@@ -278,6 +278,17 @@ cg_status cg_lbm_load(cg_lbm* h, const void* src);
  * launch count and total milliseconds since the last reset (n: in =
  * capacity, out = count). */
 cg_status cg_lbm_set_timing(cg_lbm* h, int mask);
+/* Step replay from HIP graphs (on != 0): each step's launches are captured
+ * once per ping-pong parity (on a stream of the handle's own) and replayed
+ * on the handle's stream; a graph is captured again when the run's
+ * parameters (cg_lbm_set_wetting, _set_body_force, _set_pressure,
+ * _switch_inlet) or block sizes (cg_lbm_tune) have changed since.  Results
+ * are those of the plain launches, bit for bit.  Steps with kernel timing on
+ * and the first step after a state set from the host run as plain launches.
+ * on = 0 releases the graphs.  Saves the launch overhead of small runs. */
+cg_status cg_lbm_set_graph(cg_lbm* h, int on);
+/* Number of step graphs the handle has captured so far (-1: NULL handle). */
+int64_t cg_lbm_graph_captures(const cg_lbm* h);
 cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, double* total_ms, int* n);
 cg_status cg_lbm_reset_timing(cg_lbm* h);
 

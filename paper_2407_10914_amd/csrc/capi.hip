@@ -315,6 +315,14 @@ cg_status cg_lbm_set_timing(cg_lbm* h, int mask) {
   return CG_OK;
 }
 
+cg_status cg_lbm_set_graph(cg_lbm* h, int on) {
+  if (!h) return fail(CG_EINVAL, "NULL handle");
+  h->eng->set_graph(on != 0);
+  return CG_OK;
+}
+
+int64_t cg_lbm_graph_captures(const cg_lbm* h) { return h ? h->eng->graph_captures() : -1; }
+
 cg_status cg_lbm_set_wetting(cg_lbm* h, double theta_deg, const double* theta_field_deg) {
   if (!h) return fail(CG_EINVAL, "NULL handle");
   if (!theta_field_deg && !(theta_deg > 0.0 && theta_deg < 180.0))

@@ -41,6 +41,8 @@ class Engine final : public EngineBase {
  public:
   ~Engine() override {
     if (stream_) (void)hipStreamSynchronize(stream_);
+    drop_step_graphs();
+    if (g_stream_) (void)hipStreamDestroy(g_stream_);
     for (void* p : owned_) al_->put(p);
     for (auto& ev : ev_pool_) (void)hipEventDestroy(ev);
   }
@@ -252,15 +254,30 @@ class Engine final : public EngineBase {
 
   int step(int64_t n) override {
     for (int64_t k = 0; k < n; ++k) {
-      if (dim_ == 3)
+      if (graph_on_ && !pre_ && timing_ == 0) {
+        const int rc = graph_step();
+        if (rc != CG_OK) return rc;
+      } else if (dim_ == 3) {
         one_step<3>();
-      else
+      } else {
         one_step<2>();
+      }
       ++t;
     }
     CG_HIP(hipGetLastError());
     return CG_OK;
   }
+
+  // Steps replayed from captured graphs: one graph per ping-pong parity (the
+  // launches of one step from the state in buffer c), captured on the run's
+  // stream the first time it is needed and again whenever the parameters the
+  // kernels take by value or the block sizes have changed since.  The graphs
+  // hold kernel launches only.
+  void set_graph(bool on) override {
+    graph_on_ = on;
+    if (!on) drop_step_graphs();
+  }
+  int64_t graph_captures() const override { return g_captures_; }
 
   int macro(double* rr, double* rb, double* u, double* kap, double* F, double* C) override {
     MacroOut mo{rr, rb, nullptr, u, kap, F, C};
@@ -568,6 +585,65 @@ class Engine final : public EngineBase {
     else
       return OutCanon<Real, D>{fr_[c ^ 1], fb_[c ^ 1], P_.Np};
   }
+  uint64_t graph_key() const {
+    uint64_t h = params_version * 1000003ull;
+    for (int k = 0; k < K_COUNT; ++k) h = h * 31ull + (uint64_t)bs_[k];
+    return h;
+  }
+  void drop_step_graphs() {
+    // replays still queued on the run's stream finish before their graph goes
+    if (g_exec_[0] || g_exec_[1]) (void)hipStreamSynchronize(stream_);
+    for (int p = 0; p < 2; ++p) {
+      if (g_exec_[p]) (void)hipGraphExecDestroy(g_exec_[p]);
+      if (g_graph_[p]) (void)hipGraphDestroy(g_graph_[p]);
+      g_exec_[p] = nullptr;
+      g_graph_[p] = nullptr;
+    }
+  }
+  int graph_step() {
+    const int p = cur_;
+    const uint64_t key = graph_key();
+    if (g_exec_[p] && g_key_[p] != key) drop_step_graphs();
+    if (!g_exec_[p]) {
+      // captured on a private stream (the run's stream may be the null
+      // stream, which cannot be captured); replayed on the run's stream
+      if (!g_stream_ && hipStreamCreateWithFlags(&g_stream_, hipStreamNonBlocking) != hipSuccess) {
+        g_stream_ = nullptr;
+        err_ = "hipStreamCreateWithFlags failed";
+        return CG_EHIP;
+      }
+      if (hipStreamBeginCapture(g_stream_, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        err_ = "hipStreamBeginCapture failed";
+        return CG_EHIP;
+      }
+      hipStream_t run_stream = stream_;
+      stream_ = g_stream_;
+      if (dim_ == 3)
+        step_with<3>(in_post<3>());
+      else
+        step_with<2>(in_post<2>());
+      stream_ = run_stream;
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(g_stream_, &g);
+      if (e != hipSuccess || !g) {
+        err_ = std::string("step graph capture: ") + hipGetErrorString(e);
+        return CG_EHIP;
+      }
+      if (hipGraphInstantiate(&g_exec_[p], g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        g_exec_[p] = nullptr;
+        err_ = "hipGraphInstantiate failed";
+        return CG_EHIP;
+      }
+      g_graph_[p] = g;
+      g_key_[p] = key;
+      ++g_captures_;
+    }
+    CG_HIP(hipGraphLaunch(g_exec_[p], stream_));
+    cur_ ^= 1;
+    return CG_OK;
+  }
+
   // account for n steps taken by a batch launch
   void advance(int64_t n) {
     if (n & 1) cur_ ^= 1;
@@ -597,6 +673,12 @@ class Engine final : public EngineBase {
   static_assert(K_COUNT == 7, "one default block size per kernel");
   int bs_[K_COUNT] = {256, 256, 256, 256, 256, 256, 256};
   bool pre_ = true;
+  bool graph_on_ = false;
+  hipGraph_t g_graph_[2] = {nullptr, nullptr};
+  hipGraphExec_t g_exec_[2] = {nullptr, nullptr};
+  uint64_t g_key_[2] = {0, 0};
+  hipStream_t g_stream_ = nullptr;
+  int64_t g_captures_ = 0;
   Real* fr_[2] = {nullptr, nullptr};
   Real* fb_[2] = {nullptr, nullptr};
   float* T_[2] = {nullptr, nullptr};

@@ -78,6 +78,8 @@ struct EngineBase {
   virtual int tune(int reps, std::string* report) = 0;
   virtual void blocks(int* out) const = 0;
   virtual void set_timing(int mask) = 0;
+  virtual void set_graph(bool on) = 0;
+  virtual int64_t graph_captures() const = 0;
   virtual int kernel_times(int64_t* counts, double* ms) = 0;
   virtual void reset_timing() = 0;
   virtual size_t state_bytes() const = 0;

@@ -26,7 +26,8 @@ FIELDS = {"rho_r": (0, 1), "rho_b": (1, 1), "phi": (2, 1), "u": (3, 3), "f_r": (
 EXPORTS = ("cg_options_default", "cg_lbm_create", "cg_lbm_destroy", "cg_last_error", "cg_lbm_set_phase",
            "cg_lbm_set_state", "cg_lbm_step", "cg_lbm_sync", "cg_lbm_time", "cg_lbm_observe",
            "cg_lbm_get_field", "cg_lbm_info", "cg_lbm_snapshot_bytes", "cg_lbm_save", "cg_lbm_load",
-           "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing", "cg_batch_create",
+           "cg_lbm_set_timing", "cg_lbm_kernel_times", "cg_lbm_reset_timing", "cg_lbm_set_graph",
+           "cg_lbm_graph_captures", "cg_batch_create",
            "cg_batch_destroy", "cg_batch_step", "cg_batch_sync", "cg_batch_set_graph", "cg_batch_tune",
            "cg_batch_info", "cg_batch_observe", "cg_lbm_set_wetting", "cg_lbm_set_body_force", "cg_lbm_adjoint",
            "cg_lbm_tune", "cg_lbm_set_pressure", "cg_lbm_switch_inlet", "cg_lbm_line_crossings",
@@ -153,6 +154,9 @@ def load():
     L.cg_lbm_save.argtypes = [p, p]
     L.cg_lbm_load.argtypes = [p, p]
     L.cg_lbm_set_timing.argtypes = [p, i]
+    L.cg_lbm_set_graph.argtypes = [p, i]
+    L.cg_lbm_graph_captures.argtypes = [p]
+    L.cg_lbm_graph_captures.restype = C.c_int64
     L.cg_lbm_kernel_times.argtypes = [p, p, p, p, C.POINTER(C.c_int)]
     L.cg_lbm_reset_timing.argtypes = [p]
     L.cg_lbm_tune.argtypes = [p, i, C.c_char_p, C.c_size_t]

@@ -258,6 +258,15 @@ class Sim:
     # ---------------------------------------------------------------- timing
     KERNELS = ("k_phase", "k_sb_phi", "k_normal", "k_sb_n", "k_curv", "k_main", "k_face")
 
+    def set_graph(self, on=True):
+        """Replay steps from captured HIP graphs (same results, less launch
+        overhead for small runs)."""
+        L.check(L.load().cg_lbm_set_graph(self._h, 1 if on else 0))
+
+    @property
+    def graph_captures(self):
+        return L.load().cg_lbm_graph_captures(self._h)
+
     def set_timing(self, kernels="all"):
         """Bracket launches of the named kernels with HIP events ("all", None,
         or an iterable of names)."""

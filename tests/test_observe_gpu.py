@@ -117,6 +117,10 @@ def test_non_finite_state_is_reported_unstable(precision):
     case, kw = c2_tube(scheme=1, theta=45.0, drive="type1", nz=24, radius=6.0, wet_len=8)
     g = gpu(case, kw, precision)
     g.step(5)
+    snap = g.save()  # the checkpoint a driver rolls back to
+    ref = gpu(case, kw, precision)
+    ref.step(5)
+    ref.step(4)
     fr, fb = g.populations()
     z, y, x = 12, case.solid.shape[1] // 2, case.solid.shape[2] // 2
     assert case.solid[z, y, x] == 0
@@ -131,3 +135,9 @@ def test_non_finite_state_is_reported_unstable(precision):
     g.step(3)
     with pytest.raises(CgError):
         g.observe()
+    # roll back to the checkpoint: the run continues as if nothing happened
+    g.load(snap)
+    g.step(4)
+    a, b = g.populations(), ref.populations()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert g.observe()["nan_count"] == 0
