@@ -93,9 +93,10 @@ def settle(sim, region, *, check, window, tol, min_steps, max_steps):
 
 
 def run_protocol(sim, *, drive, region, length, drainage=DRAINAGE, spontaneous=SPONTANEOUS, forced=FORCED,
-                 check=1000, window=3, tol=2e-3, min_steps=4000, max_steps=40000, log=None):
+                 check=1000, window=3, tol=2e-3, min_steps=4000, max_steps=40000, log=None, on_stage=None):
     """Runs the three phases on `sim` (a Sim with Zou-He faces on z, injecting
-    the non-wetting fluid, zeta_r = 1).  Returns the list of Stage records."""
+    the non-wetting fluid, zeta_r = 1).  Returns the list of Stage records;
+    on_stage(records) is called after every stage."""
     drv = Driver(sim, drive, length)
     out = []
 
@@ -105,6 +106,8 @@ def run_protocol(sim, *, drive, region, length, drainage=DRAINAGE, spontaneous=S
                                         max_steps=max_steps)
         st = Stage(phase, drho, sign * drho / 3.0, steps, obs["sat_w"], obs["sat_nw_mass"], conv, hist)
         out.append(st)
+        if on_stage:
+            on_stage(out)
         if log:
             log(f"{phase:12s} drho {drho:.4f} P_c {st.p_c:+.5f}: S_w {st.s_w:.4f} S_nw(mass) {st.s_nw_mass:.4f} "
                 f"after {steps} steps{'' if conv else ' (max steps)'}")
@@ -159,22 +162,33 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     res = {}
+    workload = (f"synthetic rock {a.n}^3, porosity 0.22, sigma 0.01, theta 30 deg Scheme-I, MRT FP32, "
+                f"tau_r 1.0 tau_b 0.6; steady when S_w moves < {a.tol} over {3 * a.check} steps, "
+                f"{a.min_steps}-{a.max_steps} steps per stage")
+
+    def dump(partial=None):
+        if a.json:
+            body = dict(res)
+            if partial:
+                body.update(partial)
+            with open(a.json, "w") as f:
+                json.dump({"workload": workload, "results": body}, f)
+
     for drive in (("type1", "type2") if a.drive == "both" else (a.drive,)):
         t0 = time.perf_counter()
         sim, case, region = rock_run(a.n, drive)
         stages = run_protocol(sim, drive=drive, region=region, length=case.solid.shape[0], check=a.check,
                               max_steps=a.max_steps, min_steps=a.min_steps, tol=a.tol,
-                              log=lambda m: print(f"[{drive}] {m}", file=sys.stderr, flush=True))
+                              log=lambda m: print(f"[{drive}] {m}", file=sys.stderr, flush=True),
+                              on_stage=lambda st: dump({drive: {"partial": True,
+                                                                "stages": [dataclasses.asdict(x) for x in st]}}))
         res[drive] = {"summary": summary(stages), "stages": [dataclasses.asdict(s) for s in stages],
                       "fluid_nodes": sim.info()["fluid"], "wall_s": round(time.perf_counter() - t0, 1)}
         print(f"[{drive}] {res[drive]['summary']}", file=sys.stderr, flush=True)
         del sim
         torch.cuda.empty_cache()
-    line = {"workload": f"synthetic rock {a.n}^3, porosity 0.22, sigma 0.01, theta 30 deg Scheme-I, MRT FP32, "
-                        "tau_r 1.0 tau_b 0.6", "results": res}
-    if a.json:
-        with open(a.json, "w") as f:
-            json.dump(line, f)
+        dump()
+    dump()
     print(json.dumps({k: v["summary"] for k, v in res.items()}))
 
 
