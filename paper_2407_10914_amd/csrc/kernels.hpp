@@ -44,6 +44,18 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
   CT phi;
   if (fl & FL_IN) {
     phi = P.phi_in;
+  } else if (std::is_same_v<In, InCompact<D>>) {
+    // the compact state: the two sums only, accumulated as the pulled
+    // populations are rebuilt in double (see pull_sums_compact); an outlet
+    // node's phase, the one of the node upstream (Eq. 39), is copied by
+    // k_face once this stage has stored that node's
+    if constexpr (std::is_same_v<In, InCompact<D>>) {
+      if (fl & FL_OUT) return;
+      CT rr, rho;
+      pull_sums_compact<D>(in, G.nbr, n, P.rho0, rr, rho);
+      phi = (rr - (rho - rr)) / rho;
+      __builtin_nontemporal_store(rr, &in.RS[n]);
+    }
   } else {
     // pulled populations rebuilt in double (for the compact float state the
     // red population is a (w rho0 + g) + w c.e of single-precision factors)
@@ -72,17 +84,15 @@ __device__ __forceinline__ void d_phase(const StepParams& P, const Geo<Real>& G,
       node_moments<D, kDev>(fr, fx, (CT)P.rho0, rr, rb, rho, drho);
     }
     phi = (rr - rb) / rho;
-    if constexpr (std::is_same_v<In, InCompact<D>>) {
-      if (!(fl & FL_OUT)) __builtin_nontemporal_store(rr, &in.RS[n]);
-    }
   }
   R.phi[vox_of(vf)] = phi_enc<typename Grids<Real>::PhiT>(phi);
 }
 
-// Zou-He face node n of the compact single-precision state (after the phase
-// stage, which stored its phase): its pulled populations with the faces
-// applied, Appendix B, in the step kernel's single-precision arithmetic.  The
-// step kernel takes the red sum and the five unknowns from here.  A kernel of
+// Zou-He face node n of the compact single-precision state, after the phase
+// stage: an outlet node first takes the stored phase of the node upstream
+// (Eq. 39); then its pulled populations with the faces applied, Appendix B,
+// in the step kernel's single-precision arithmetic.  The step kernel takes
+// the red sum and the five unknowns from here.  A kernel of
 // its own, so that the per-colour pull of these few nodes does not set the
 // register count of the phase stage.
 template <class Real, int D, class In>
@@ -92,9 +102,16 @@ __device__ __forceinline__ void d_face(const StepParams& P, const Geo<Real>& G, 
     constexpr int Q = Lat<D>::Q;
     const unsigned vf = ld_once(&G.vf[n]);
     const unsigned fl = flags_of(vf);
+    const int v = vox_of(vf);
+    auto enc = R.phi[v];
+    if (fl & FL_OUT) {
+      // Eq. (39): the phase of the node upstream, as the phase stage stored it
+      enc = R.phi[v - P.nx * P.ny];
+      R.phi[v] = enc;
+    }
     float fr[Q], fx[Q];
     load_node<D>(in, G.nbr, n, fr, fx);
-    zou_he<true>(P, fl, (float)phi_dec(R.phi[vox_of(vf)]), fr, fx);
+    zou_he<true>(P, fl, (float)phi_dec(enc), fr, fx);
     double rs = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) rs = rs + (double)fr[i];

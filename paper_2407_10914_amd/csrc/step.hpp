@@ -502,6 +502,88 @@ struct InCompact {
   }
 };
 
+// Leading components of a node's (a, c) record that direction i uses: a and
+// c up to the last axis along which e_i is not zero (one load per
+// direction, narrower where it can be).
+template <int D, int i>
+constexpr int ac_width() {
+  return Lat<D>::e(i, 2) != 0 ? 4 : (Lat<D>::e(i, 1) != 0 ? 3 : (Lat<D>::e(i, 0) != 0 ? 2 : 1));
+}
+template <int W>
+struct ACw;
+template <>
+struct alignas(8) ACw<2> {
+  float a, c0;
+};
+template <>
+struct ACw<3> {
+  float a, c0, c1;
+};
+template <>
+struct alignas(16) ACw<4> {
+  float a, c0, c1, c2;
+};
+
+// Red and total density pulled into node n of the compact state, summed in
+// double over i ascending as they are rebuilt (the rest population first):
+// the same values and the same order of additions as rebuilding every pulled
+// population with InCompact::finish_pull in double and summing afterwards,
+// without keeping the rebuilt populations.  The loads are issued as in
+// load_node; each direction reads only the components of (a, c) it uses.
+template <int D>
+__device__ __forceinline__ void pull_sums_compact(const InCompact<D>& in, const Nbr& nbr, int n, double rho0,
+                                                  double& red, double& tot) {
+  constexpr int Q = Lat<D>::Q;
+  const float t0 = in.T[n];
+  const float a0 = in.AC[n].x;
+  __builtin_amdgcn_sched_barrier(0);
+  int src[Q];
+  nbr.template all<Q>(n, src);
+  float tr[Q];
+  float ra[Q], rc0[Q], rc1[Q], rc2[Q];
+  // per direction, bit i: the source is a fluid node (else bounce-back from
+  // the node itself), and the link crosses an open face (a zero); the table
+  // entries themselves are not needed once the loads are issued
+  uint32_t fluid_bits = 0u, open_bits = 0u;
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    constexpr int o = opp<D>(i);
+    constexpr int W = ac_width<D, i>();
+    const bool fl = src[i] >= 0;
+    fluid_bits |= fl ? (1u << i) : 0u;
+    open_bits |= src[i] < kBounce ? (1u << i) : 0u;
+    int node = fl ? src[i] : n;
+    int row = fl ? i * in.Np : o * in.Np;
+    asm("" : "+v"(node), "+v"(row));
+    tr[i] = in.T[row + node];
+    const ACw<W> q = *reinterpret_cast<const ACw<W>*>(&in.AC[node]);
+    ra[i] = q.a;
+    rc0[i] = q.c0;
+    if constexpr (W >= 3) rc1[i] = q.c1;
+    if constexpr (W >= 4) rc2[i] = q.c2;
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  const double w0 = Lat<D>::w(0);
+  double r = (double)a0 * (w0 * (double)in.rho0 + (double)t0);
+  double t = w0 * rho0 + (double)t0;
+  unroll<Q - 1>([&](auto I) {
+    constexpr int i = I + 1;
+    constexpr int W = ac_width<D, i>();
+    constexpr double w = Lat<D>::w(i);
+    const bool fl = fluid_bits & (1u << i);
+    const double g = (double)tr[i];
+    double ce = (double)(float)Lat<D>::e(i, 0) * (double)rc0[i];
+    if constexpr (W >= 3) ce = ce + (double)(float)Lat<D>::e(i, 1) * (double)rc1[i];
+    if constexpr (W >= 4) ce = ce + (double)(float)Lat<D>::e(i, 2) * (double)rc2[i];
+    const double r0 = (double)ra[i] * (w * (double)in.rho0 + g) + w * (fl ? ce : -ce);
+    const bool open = open_bits & (1u << i);
+    r = r + (open ? 0.0 : r0);
+    t = t + (w * rho0 + (open ? 0.0 : g));
+  });
+  red = r;
+  tot = t;
+}
+
 // Unknown directions of the inlet and of the outlet (Eqs. B.1-B.18): the
 // populations that enter the domain through the face.
 constexpr int kZhIn[5] = {5, 11, 12, 15, 16};
