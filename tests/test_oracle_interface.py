@@ -202,3 +202,31 @@ def test_fictitious_density_sessile_angles_follow_the_input():
         got[th] = 180.0 - measure.drop_angle(o.macro()["phi"][0])
         assert abs(got[th] - th) < 8.0, got
     assert got[60.0] < 90.0 < got[120.0]
+
+
+def test_slab_observables_add_up_over_complementary_slabs():
+    """Observables restricted to lo <= z < hi: the full range gives the
+    unrestricted values, two complementary slabs add up to the whole (counts,
+    masses and volumes; saturations weighted by their node counts), an empty
+    slab holds nothing, and the plane flux ignores the slab."""
+    case, kw = c2_tube(scheme=1, theta=45.0, drive="type1", nz=30, radius=6.0, wet_len=12)
+    o = O.OracleSim(case.solid, **kw)
+    o.set_phase(case.phi0)
+    o.step(20)
+    nz = case.solid.shape[0]
+    whole = o.observe(axis=2, plane=7)
+    full = o.observe(axis=2, plane=7, slab=(2, 0, nz))
+    for k, v in whole.items():
+        assert full[k] == v, k
+    for cut in (1, 11, 12, 13, nz - 1):
+        a = o.observe(axis=2, plane=7, slab=(2, 0, cut))
+        b = o.observe(axis=2, plane=7, slab=(2, cut, nz))
+        for k in ("n_fluid", "mass_r", "mass_b", "vol_r", "vol_b", "n_in", "n_out"):
+            assert abs(a[k] + b[k] - whole[k]) <= 1e-12 * abs(whole[k]), (cut, k)
+        nw = a["sat_w"] * a["n_fluid"] + b["sat_w"] * b["n_fluid"]
+        assert abs(nw - whole["sat_w"] * whole["n_fluid"]) <= 1e-9, cut
+        assert a["flux_t"] == b["flux_t"] == whole["flux_t"]
+        # plane z = cut belongs to the upper slab only
+        assert a["n_fluid"] == (case.solid[:cut] == 0).sum()
+    empty = o.observe(axis=2, plane=7, slab=(2, 5, 5))
+    assert empty["n_fluid"] == 0 and empty["mass_r"] == 0 and empty["sat_w"] == 0
