@@ -51,10 +51,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_fluid, block):
-    """HBM bytes per k_main launch from the committed rocprofv3 PMC summary,
-    or None when missing, taken from other kernel sources or at another
-    block size."""
+def read_profile(n_fluid, block):
+    """The committed rocprofv3 PMC summary's figures (HBM bytes per k_main
+    launch, measured bytes per fluid node over the whole step), or None when
+    missing, taken from other kernel sources or at another block size."""
     path = os.path.join(ROOT, "profiles", "k_main_rock256_f32_pmc.md")
     if not os.path.exists(path):
         return None
@@ -67,7 +67,13 @@ def read_traffic(n_fluid, block):
         return None
     if meta.get("block", 256) != block:
         return None
-    return meta.get("bytes_per_launch")
+    return meta
+
+
+def read_traffic(n_fluid, block):
+    """HBM bytes per k_main launch from the committed profile (see read_profile)."""
+    meta = read_profile(n_fluid, block)
+    return None if meta is None else meta.get("bytes_per_launch")
 
 
 def cpu_baseline(case, kw, budget_s=20.0, threads=None):
@@ -264,6 +270,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run the library's plain 1 GiB copy kernel (reference for the HBM byte counters)")
     ap.add_argument("--windows", type=int, default=5, help="timed windows the --steps are split into (median)")
+    ap.add_argument("--graph", action="store_true", help="replay the timed steps from captured HIP graphs")
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the streaming-kernel sweep that measures the HBM ceiling")
     args = ap.parse_args()
@@ -291,6 +298,8 @@ def main():
         print(f"# tuned: {tuning}", file=sys.stderr, flush=True)
     main_block = int(tuning.split("k_main: block ")[1].split()[0]) if tuning else 256
 
+    if args.graph:
+        sim.set_graph(True)  # the warm-up captures the two step graphs
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -335,6 +344,11 @@ def main():
             "block": main_block}
     step_frac = mlups * 1e6 * B_ALG_F32_D3Q19 / (HBM_PEAK_GBS * 1e9)
     roof["step_hbm_frac_alg"] = round(step_frac, 4)  # the whole step's algorithmic rate against the peak
+    prof = read_profile(n_fluid, main_block)
+    if prof and prof.get("step_bytes_per_node"):
+        # measured HBM bytes of all step kernels per fluid-node update (counters) at this run's step rate
+        roof["step_traffic_bytes_per_node"] = prof["step_bytes_per_node"]
+        roof["step_traffic_gbs"] = round(prof["step_bytes_per_node"] * mlups * 1e6 / 1e9, 1)
     ceiling = None
     if not args.no_ceiling:
         from paper_2407_10914_amd import roofline
@@ -408,7 +422,8 @@ def main():
                    "fluid_nodes": n_fluid, "voxels": info["voxels"], "voxel_mlups": round(vox_mlups, 1),
                    "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3),
                    "timing": {"windows": nw, "steps_per_window": sizes, "window_ms": [round(w, 4) for w in win_ms],
-                              "value_is": "median window", "mlups_all_windows": round(mlups_all, 1)},
+                              "value_is": "median window", "mlups_all_windows": round(mlups_all, 1),
+                              "launches": "hipGraph replay" if args.graph else "plain"},
                    "hbm_ceiling": ceiling,
                    "sat_nw_mass": obs["sat_nw_mass"], "tuning": tuning,
                    "saturation_curve": None if curve is None else {"columns": ["step", "S_nw_mass", "S_w"],
