@@ -131,14 +131,18 @@ __host__ __device__ inline int face_tiles_in(const StepParams& P) { return (P.n_
 __host__ __device__ inline int face_tiles(const StepParams& P) {
   return P.n_out > 0 ? face_tiles_in(P) + ((P.N + 63) >> 6) - ((P.N - P.n_out) >> 6) : face_tiles_in(P);
 }
-template <class Real, int D, class In>
-__global__ void k_face(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
-  const int t = node_id_plain();
+// The face node thread t of the launch works on, or -1.
+__host__ __device__ inline int face_node(const StepParams& P, int t) {
   const int w = t >> 6, lane = t & 63, tin = face_tiles_in(P);
-  if (w >= face_tiles(P)) return;
+  if (t < 0 || w >= face_tiles(P)) return -1;
   const int n = w < tin ? (w << 6) + lane : ((((P.N - P.n_out) >> 6) + w - tin) << 6) + lane;
   const bool face = w < tin ? n < P.n_in : (n >= P.N - P.n_out && n < P.N);
-  if (face) d_face<Real, D, In>(P, G, R, in, n);
+  return face ? n : -1;
+}
+template <class Real, int D, class In>
+__global__ void k_face(StepParams P, Geo<Real> G, Grids<Real> R, In in) {
+  const int n = face_node(P, node_id_plain());
+  if (n >= 0) d_face<Real, D, In>(P, G, R, in, n);
 }
 
 template <class Real, int D, class In>

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "kernels.hpp"
 #include "setup.hpp"
 #include "step.hpp"
 
@@ -119,9 +120,49 @@ void run(const char* name, int dim, int nx, int ny, int nz, const uint8_t per[3]
   }
 }
 
+// The face kernel's launch covers whole 64-node tiles (the pull table
+// decodes per tile): wave w takes the w-th tile holding inlet nodes, then the
+// tiles holding outlet nodes.  Every face node must come up exactly once,
+// and each wave's nodes must lie in one tile.
+void face_tile_mapping() {
+  Lcg r{99};
+  for (int trial = 0; trial < 4000; ++trial) {
+    cg::StepParams P{};
+    P.N = 1 + (int)(r.uni() * 5000);
+    P.n_in = (int)(r.uni() * (P.N + 1));
+    if (P.n_in > P.N) P.n_in = P.N;
+    P.n_out = (int)(r.uni() * (P.N - P.n_in + 1));
+    if (P.n_out > P.N - P.n_in) P.n_out = P.N - P.n_in;
+    std::vector<int> seen(P.N, 0);
+    const int T = cg::face_tiles(P);
+    bool ok = true;
+    for (int w = 0; w < T; ++w) {
+      int tile = -1;
+      for (int lane = 0; lane < 64; ++lane) {
+        const int n = cg::face_node(P, (w << 6) + lane);
+        if (n < 0) continue;
+        if (n < 0 || n >= P.N) ok = false;
+        else seen[n] += 1;
+        if (tile < 0) tile = n >> 6;
+        if ((n >> 6) != tile) ok = false;
+      }
+    }
+    for (int n = 0; n < P.N; ++n) {
+      const bool want = n < P.n_in || n >= P.N - P.n_out;
+      if (seen[n] != (want ? 1 : 0)) ok = false;
+    }
+    if (!ok) {
+      check(false, "face tile mapping N=" + std::to_string(P.N) + " in=" + std::to_string(P.n_in) +
+                       " out=" + std::to_string(P.n_out));
+      return;
+    }
+  }
+}
+
 }  // namespace
 
 int main() {
+  face_tile_mapping();
   Lcg r{2407};
   {
     // 3D channel with random solids, Zou-He z, walls on x and y
