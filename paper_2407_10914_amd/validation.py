@@ -264,8 +264,13 @@ def main(argv=None):
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--steps", type=int, default=None,
                     help="steps of the Laplace and contact-angle runs (default 10000 and 20000)")
+    ap.add_argument("--schemes", default=None,
+                    help="wetting schemes of the contact-angle sweep, e.g. 1,2,3 (3: fictitious density, Eq. 24)")
     a = ap.parse_args(argv)
     extra = {} if a.steps is None else {"steps": a.steps}
+    angle_extra = dict(extra)
+    if a.schemes:
+        angle_extra["schemes"] = tuple(int(x) for x in a.schemes.split(","))
     import torch
 
     torch.cuda.set_device(0)
@@ -276,7 +281,7 @@ def main(argv=None):
         if w == "laplace":
             res[w] = laplace_sweep(precision=a.precision, log=log, **extra)
         elif w == "angle":
-            res[w] = angle_sweep(precision=a.precision, log=log, **extra)
+            res[w] = angle_sweep(precision=a.precision, log=log, **angle_extra)
         else:
             res[w] = washburn_runs(precision=a.precision, log=log)
         res[w]["wall_s"] = round(time.perf_counter() - t0, 1)
