@@ -70,8 +70,7 @@ typedef struct {
  * fictitious-density model (Eq. 24) instead fixes the phase of every solid
  * boundary point to -cos(theta) (Eq. 24 written for an angle measured
  * through fluid b: cos of the angle through fluid r) and leaves the normals
- * as the colour gradient gives them.  The adjoint covers Scheme-I and
- * Scheme-II only. */
+ * as the colour gradient gives them.  The adjoint covers all three. */
 enum { CG_WET_NONE = 0, CG_WET_SCHEME1 = 1, CG_WET_SCHEME2 = 2, CG_WET_FICTITIOUS = 3 };
 /* Scheme-I secant start: SIGN_RULE takes v1 = n_c - (n_c + s n_w)/2 with
  * s = +1 for theta > 90 deg and s = -1 otherwise; LITERAL keeps s = +1 (Eq. 30
@@ -394,6 +393,9 @@ cg_status cg_lbm_drop_shape(cg_lbm* h, int base_axis, int wall_axis, int slice, 
  * Scheme-II candidate choice) with respect to the global contact angle (per
  * degree; with a per-voxel field it is the derivative along a uniform shift
  * of the field), the per-voxel field, and the body-force acceleration g.
+ * With the fictitious-density model the angle enters through the fixed phase
+ * -cos(theta) of each solid boundary point (Eq. 24), so the field gradient
+ * sits on those points' own voxels.
  * The forward sweep stores the state every checkpoint_every = K steps; the
  * reverse sweep recomputes the K states of one segment at a time into a ring
  * of K state buffers, so the device memory held during the call is about

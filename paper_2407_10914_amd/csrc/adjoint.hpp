@@ -908,6 +908,27 @@ __device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs
 template <class Real, int D>
 __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   const int s = node_id_plain();
+  if (P.scheme == 3) {
+    // fictitious density, Eq. (24): phi(x_s) = -cos(theta(x_s)) is a
+    // parameter, not a mean of the fluid neighbours, so its adjoint goes to
+    // the contact angle, d phi / d theta = sin(theta) pi/180 per degree
+    // (sin >= 0 on (0, 180) deg), and nothing flows back to the fluid phase
+    double lth = 0.0;
+    if (s < P.nsb) {
+      const int v = G.sb_vox[s];
+      const unsigned m = G.sb_mask[s];
+      const Pos ps = make_pos(P, v, m & 1u);
+      int nbi[Lat<D>::Q];
+      nb_all<D>(P, ps, nbi);
+      const double lp = (double)adj_grad_t_sb<Real, D>(P, A, nbi, m);
+      const double c = (double)G.sb_fd[s];
+      lth = lp * ::sqrt(::fmax(0.0, 1.0 - c * c)) * (M_PI / 180.0);
+      A.lphi[v] = Real(0);
+      A.lth[v] += lth;
+    }
+    block_accumulate<256, 1>(&lth, 3, A.pacc);
+    return;
+  }
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
   const unsigned m = G.sb_mask[s];
@@ -1076,6 +1097,10 @@ __global__ void ka_theta_field(StepParams P, Geo<Real> G, const double* lth, dou
   const int s = node_id_plain();
   if (s >= P.nsb) return;
   const int v = G.sb_vox[s];
+  if (P.scheme == 3) {
+    out[v] = lth[v];  // the point's own angle (fictitious density)
+    return;
+  }
   const unsigned m = G.sb_mask[s];
   const Pos ps = make_pos(P, v, m & 1u);
   double acc = 0.0;

@@ -33,10 +33,6 @@ class AdjointRun {
       E.err_ = "the adjoint covers closed and periodic boundaries with the body force (no Zou-He faces)";
       return CG_EUNSUPPORTED;
     }
-    if (P.scheme == 3) {
-      E.err_ = "the adjoint covers Scheme-I and Scheme-II wetting (not the fictitious-density model)";
-      return CG_EUNSUPPORTED;
-    }
     if (sp.n_steps < 1 || sp.checkpoint_every < 1) {
       E.err_ = "n_steps and checkpoint_every must be >= 1";
       return CG_EINVAL;
@@ -70,6 +66,7 @@ class AdjointRun {
   Real *lk_ = nullptr, *lphi_ = nullptr, *iden_ = nullptr;
   double *idf_ = nullptr, *lth_ = nullptr, *part_ = nullptr, *sums_ = nullptr;
   double* pacc_ = nullptr;
+  int npacc_ = 0;  // rows of pacc_
   // front fields (phase, normal, colour gradient, force) of the state at
   // t0 + k for each ring index k, kept from the recomputation so the reverse
   // step does not evaluate the front stages again; empty when the memory was
@@ -241,7 +238,10 @@ class AdjointRun {
     idf_ = (double*)get(sizeof(double) * Np);
     lth_ = (double*)get(sizeof(double) * V);
     const int nb = (P.N + BS - 1) / BS;
-    pacc_ = (double*)get(sizeof(double) * 4 * (size_t)nb);
+    // parameter rows: one per block of the node kernels and of the solid
+    // boundary kernel (the fictitious-density angle adjoint)
+    npacc_ = std::max(nb, (P.nsb + BS - 1) / BS);
+    pacc_ = (double*)get(sizeof(double) * 4 * (size_t)npacc_);
     part_ = (double*)get(sizeof(double) * 4 * (size_t)(nb + 1));
     sums_ = (double*)get(sizeof(double) * 8);
     ok = ok && lf_[0] && lf_[1] && lr_ && na_ && lcf_ && lk_ && ln_ && lc_ && lphi_ && iden_ && idf_ && lth_ &&
@@ -261,7 +261,7 @@ class AdjointRun {
     zero(lphi_, sizeof(Real) * V);
     zero(iden_, sizeof(Real) * V);
     zero(lth_, sizeof(double) * V);
-    zero(pacc_, sizeof(double) * 4 * (size_t)nb);
+    zero(pacc_, sizeof(double) * 4 * (size_t)npacc_);
     zero(lr_, sizeof(V2) * Np);
     zero(sums_, sizeof(double) * 8);
     // grid voxels that no stage writes (interior solid) are read as zeros
@@ -349,7 +349,7 @@ class AdjointRun {
     (void)hipEventRecord(e2, st);
 
     // parameter gradients
-    hipLaunchKernelGGL(ka_reduce<Real>, dim3(4), dim3(256), 0, st, (const double*)pacc_, nb, 4, sums_ + 4);
+    hipLaunchKernelGGL(ka_reduce<Real>, dim3(4), dim3(256), 0, st, (const double*)pacc_, npacc_, 4, sums_ + 4);
     if (g->dJ_dtheta_field) {
       const size_t nbv = (V + 255) / 256;
       hipLaunchKernelGGL((ka_fill<Real, double>), dim3((unsigned)nbv), dim3(256), 0, st, V, g->dJ_dtheta_field, 0.0);

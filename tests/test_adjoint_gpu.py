@@ -1,7 +1,9 @@
 """GPU adjoint (cg_lbm_adjoint) against the oracle's discrete derivative.
 
 The oracle differentiates the same n steps in forward mode on dual numbers;
-the GPU runs the reverse kernels.  For a direction d in parameter space the
+the GPU runs the reverse kernels (Scheme-I, Scheme-II, and the
+fictitious-density model, whose solid-boundary phase -cos(theta) carries the
+angle derivative directly).  For a direction d in parameter space the
 two must agree: <grad J, d> (GPU) = dJ[d] (oracle).  FP64 agrees to rounding;
 FP32 to 1e-4 relative (the bound on gradients against finite differences).
 The workload size itself (128^3 drainage rock, 2000 steps) is in
@@ -87,7 +89,7 @@ def test_checkpoint_interval_does_not_change_the_result():
         assert after[k] == ref[k]
 
 
-@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
 def test_fp64_3d_theta_field_matches_oracle_tangent(scheme):
     solid, phi0, kw = tiny_rock(scheme)
     nz = solid.shape[0]
@@ -120,7 +122,7 @@ def test_fp64_3d_theta_field_matches_oracle_tangent(scheme):
     assert rel(r2["dJ_dg"][2], d_gz) <= 1e-9
 
 
-@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
 def test_fp32_3d_matches_oracle_tangent(scheme):
     solid, phi0, kw = tiny_rock(scheme)
     nz = solid.shape[0]
