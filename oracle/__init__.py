@@ -43,7 +43,7 @@ class TangentSpec(C.Structure):
 
 
 OBJECTIVES = {"sat_nw": 0, "red_volume": 1, "flux": 2}
-SEEDS = {"theta": 0, "gx": 1, "gy": 2, "gz": 3, "theta_field": 4}
+SEEDS = {"theta": 0, "gx": 1, "gy": 2, "gz": 3, "theta_field": 4, "rho_in": 5, "rho_out": 6}
 
 
 def lib():
@@ -277,8 +277,8 @@ class OracleSim:
         """(J, dJ) after n_steps from the rest state of phi0, dJ the exact
         discrete directional derivative (forward mode, dual numbers) along the
         seeded parameter: "theta" (global angle, per degree), "gx"/"gy"/"gz"
-        (body-force acceleration) or "theta_field" along theta_dir (dense
-        voxel array, degrees)."""
+        (body-force acceleration), "rho_in"/"rho_out" (Zou-He densities) or
+        "theta_field" along theta_dir (dense voxel array, degrees)."""
         sp = TangentSpec()
         sp.objective = OBJECTIVES.get(objective, objective)
         sp.axis, sp.lo, sp.hi, sp.n_steps = axis, lo, hi, int(n_steps)

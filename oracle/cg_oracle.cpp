@@ -387,7 +387,7 @@ void scheme2(int dim, R* n, const double* nw, R cos_t, R sin_t, double eps_v) {
 /* Zou-He (non-equilibrium bounce-back) pressure inlet at z = 0 for one colour,
  * Eqs. (B.1)-(B.8); rho_s = rho_in * zeta^s. Unknowns: 5, 11, 12, 15, 16. */
 template <class R>
-void zouhe_in_color(R* f, double rho_s) {
+void zouhe_in_color(R* f, R rho_s) {
   R S = f[0] + f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[9] + f[10];
   R T = f[6] + f[13] + f[14] + f[17] + f[18];
   R j = rho_s - (S + 2.0 * T);
@@ -404,7 +404,7 @@ void zouhe_in_color(R* f, double rho_s) {
  * from the total populations, shared between colours by chi^s(phi) with phi
  * taken one node upstream (Eq. 39). Unknowns: 6, 13, 14, 17, 18. */
 template <class R>
-void zouhe_out(R* fr, R* fb, double rho_out, R phi_up) {
+void zouhe_out(R* fr, R* fb, R rho_out, R phi_up) {
   R ft[19];
   for (int i = 0; i < 19; ++i) ft[i] = fr[i] + fb[i];
   R S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
@@ -442,6 +442,7 @@ struct Sim {
   std::vector<int> s1_sign;
   R theta_global;
   R gforce[3];
+  R rho_in_v, rho_out_v; /* Zou-He densities (parameters of the derivative) */
   std::vector<R> fr, fb, pr, pb;        /* state [Q][V] and post-collision */
   std::vector<R> rr, rb, rho, phi, kap; /* [V] */
   std::vector<R> cvec, nvec, frc, uvel; /* [3][V] */
@@ -581,6 +582,8 @@ struct Sim {
     if (theta_field)
       for (long v = 0; v < V; ++v) theta_vox[v] = theta_field[v];
     for (int a = 0; a < 3; ++a) gforce[a] = p.g[a];
+    rho_in_v = p.rho_in;
+    rho_out_v = p.rho_out;
     setup_wall_normal();
     map_contact_angle();
     const size_t n = (size_t)Q * V;
@@ -764,6 +767,8 @@ struct Sim {
     if (!(rho_in > 0.0) || !(rho_out > 0.0)) return fail("densities must be positive");
     p.rho_in = rho_in;
     p.rho_out = rho_out;
+    rho_in_v = rho_in;
+    rho_out_v = rho_out;
     return 0;
   }
 
@@ -965,8 +970,8 @@ struct Sim {
               a[i] = fr[(size_t)i * V + vi];
               b[i] = fb[(size_t)i * V + vi];
             }
-            zouhe_in_color(a, p.rho_in * zr);
-            zouhe_in_color(b, p.rho_in * zb);
+            zouhe_in_color(a, rho_in_v * zr);
+            zouhe_in_color(b, rho_in_v * zb);
             for (int i = 0; i < 19; ++i) {
               fr[(size_t)i * V + vi] = a[i];
               fb[(size_t)i * V + vi] = b[i];
@@ -986,7 +991,7 @@ struct Sim {
               a[i] = fr[(size_t)i * V + vo];
               b[i] = fb[(size_t)i * V + vo];
             }
-            zouhe_out(a, b, p.rho_out, phi_up);
+            zouhe_out(a, b, rho_out_v, phi_up);
             for (int i = 0; i < 19; ++i) {
               fr[(size_t)i * V + vo] = a[i];
               fb[(size_t)i * V + vo] = b[i];
@@ -1262,6 +1267,12 @@ int orc_tangent(const orc_params* p, const uint8_t* solid, const double* theta_f
     m.theta_global = Dual(p->theta_deg, 1.0);
   } else if (spec->seed >= 1 && spec->seed <= 3) {
     m.gforce[spec->seed - 1] = Dual(p->g[spec->seed - 1], 1.0);
+  } else if (spec->seed == 5 || spec->seed == 6) {
+    if (p->bc != 1) return fail("seeds 5 and 6 need Zou-He faces");
+    if (spec->seed == 5)
+      m.rho_in_v = Dual(p->rho_in, 1.0);
+    else
+      m.rho_out_v = Dual(p->rho_out, 1.0);
   } else if (spec->seed == 4) {
     if (!theta_field_deg || !spec->theta_dir) return fail("seed 4 needs a theta field and a direction");
     m.theta_vox_r.assign(m.V, 0.0);

@@ -100,7 +100,8 @@ int orc_setup_info(const orc_sim* s, uint8_t* cls, double* g3, double* nw3,
  * directional derivative and returns J and dJ along the seeded parameter:
  * seed 0: theta (global, degrees; requires no theta field), seed 1..3: the
  * x/y/z component of the body-force acceleration g, seed 4: the per-voxel
- * contact-angle field along theta_dir (V entries, degrees).
+ * contact-angle field along theta_dir (V entries, degrees), seeds 5 and 6:
+ * the Zou-He inlet and outlet densities rho_in, rho_out (Appendix B).
  * The objectives are taken over the fluid nodes of the slab
  * lo <= coordinate[axis] < hi of the final state:
  * objective 0: non-wetting mass saturation sum rho^r / sum rho;

@@ -122,3 +122,42 @@ def test_tangent_is_linear_in_the_direction():
     t = [o.tangent(phi0, objective="sat_nw", n_steps=15, seed="theta_field", theta_dir=d, lo=3, hi=nz - 3)[1]
          for d in (d1, d2, 2.0 * d1 - 3.0 * d2)]
     assert abs(t[2] - (2.0 * t[0] - 3.0 * t[1])) <= 1e-10 * (abs(t[0]) + abs(t[1]))
+
+
+def outlet_tube(zeta_r=0.25):
+    """Short Type-I tube whose red slug sits against the outlet, so the
+    outlet plane holds mixed phase from the first steps (chi^s strictly
+    between 0 and 1, Eqs. B.12-B.18 with Eq. 39), with mixed injection at the
+    inlet (Eq. B.1)."""
+    c = inputs.tube(nx=10, ny=10, nz=14, radius=3.5, wet_len=4)
+    z = np.arange(14)[:, None, None]
+    phi0 = np.where((z >= 7) & (z < 13), 1.0, -1.0) * np.ones(c.solid.shape)
+    kw = dict(dim=3, periodic=c.periodic, tau_r=1.0, tau_b=0.7, sigma=0.02, beta=0.95, scheme=2, theta_deg=60.0,
+              bc=1, rho_in=1.04, rho_out=1.0, zeta_r=zeta_r, collision=1)
+    return c.solid, phi0, kw
+
+
+@pytest.mark.parametrize("obj,lo,hi", [("sat_nw", 0, 14), ("red_volume", 10, 14), ("flux", 13, 0), ("flux", 0, 0)])
+@pytest.mark.parametrize("seed", ["theta", "rho_in", "rho_out"])
+def test_tangent_through_the_zou_he_faces(obj, lo, hi, seed):
+    """The derivative through the inlet and outlet faces (Appendix B) and the
+    upstream phase of the outlet (Eq. 39), for objectives that include the face
+    layers, against central differences of the oracle's own runs."""
+    solid, phi0, kw = outlet_tube()
+    steps = 20
+    o = O.OracleSim(solid, **kw)
+    J, dJ = o.tangent(phi0, objective=obj, n_steps=steps, seed=seed, axis=2, lo=lo, hi=hi)
+    assert J == run(solid, phi0, kw, steps, obj, 2, lo, hi)
+    base = {"theta": ("theta_deg", 60.0, (1e-2, 1e-3)), "rho_in": ("rho_in", 1.04, (1e-4, 1e-5)),
+            "rho_out": ("rho_out", 1.0, (1e-4, 1e-5))}[seed]
+    name, v0, hs = base
+    f = lambda h: run(solid, phi0, kw, steps, obj, 2, lo, hi, **{name: v0 + h})
+    errs = [abs(central(f, h) - dJ) / abs(dJ) for h in hs]
+    assert errs[1] < 1e-6, errs
+
+
+def test_rho_seeds_need_zou_he_faces():
+    solid, phi0, kw = slug_2d()
+    o = O.OracleSim(solid, **kw)
+    with pytest.raises(Exception):
+        o.tangent(phi0, objective="sat_nw", n_steps=2, seed="rho_in", axis=0, lo=0, hi=24)
