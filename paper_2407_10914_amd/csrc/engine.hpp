@@ -792,10 +792,7 @@ class Engine final : public EngineBase {
   // solid (4), curvature and force (5)
   template <int D, class In>
   void front_with(const In& in, int upto) {
-    launch(K_PHASE, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
-    if constexpr (std::is_same_v<In, InCompact<D>>) {
-      if (P_.n_in + P_.n_out > 0) launch(K_FACE, k_face<Real, D, In>, 64 * face_tiles(P_), P_, G_, R_, in);
-    }
+    phase_with<D>(in, true);
     if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
     if (upto >= 3) launch(K_NORMAL, k_normal<Real, D>, P_.N, P_, G_, R_);
     if (upto >= 4 && nsb_) launch(K_SB_N, k_sb_n<Real, D>, nsb_, P_, G_, R_);
@@ -875,8 +872,19 @@ class Engine final : public EngineBase {
 
   template <int D, class In>
   void export_with(const In& in, double* fr, double* fb) {
-    launch(-1, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
+    phase_with<D>(in, false);
     launch(-1, k_export<Real, D, In>, P_.N, P_, G_, R_, in, fr, fb);
+  }
+  // The phase field of the state `in`; for the compact state the face kernel
+  // gives the outlet nodes the upstream phase (Eq. 39) and stores the faces'
+  // sums.  timed: under the phase and face stages' kernel timers.
+  template <int D, class In>
+  void phase_with(const In& in, bool timed) {
+    launch(timed ? K_PHASE : -1, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
+    if constexpr (std::is_same_v<In, InCompact<D>>) {
+      if (P_.n_in + P_.n_out > 0)
+        launch(timed ? K_FACE : -1, k_face<Real, D, In>, 64 * face_tiles(P_), P_, G_, R_, in);
+    }
   }
   // Pre-collision populations of the current state at their own nodes
   // (the staging that a state set from the host uses).  The double layout
@@ -885,7 +893,7 @@ class Engine final : public EngineBase {
   void materialize() {
     if (pre_) return;
     auto in = in_post<D>();
-    launch(-1, k_phase<Real, D, decltype(in)>, P_.N, P_, G_, R_, in);
+    phase_with<D>(in, false);
     if constexpr (kF32) {
       launch(-1, k_materialize<Real, D, decltype(in)>, P_.N, P_, G_, R_, in, pre_r_, pre_x_);
     } else {

@@ -703,18 +703,26 @@ __device__ __forceinline__ void load_node(const In& in, const Nbr& nbr, int n, C
   }
 }
 
-// Populations of the node upstream of outlet node n (z = nz-2), pulled entry
-// by entry (that node may lie in another tile than the wave's other nodes).
+// Populations of the node upstream of outlet node n (z = nz-2), entry by
+// entry (that node may lie in another tile than the wave's other nodes):
+// pulled for a post-streaming state, its own for a state set at the nodes.
 template <int D, class In, class CT>
 __device__ __forceinline__ void load_outlet_upstream(const In& in, const Nbr& nbr, int n, CT* fr, CT* fx) {
   constexpr int Q = Lat<D>::Q;
-  if constexpr (D == 3 && In::kPull) {
+  if constexpr (D == 3) {
     const int u = nbr.template get<kDirZp>(n);
-    in.template get<0>(u, fr[0], fx[0]);
-    unroll<Q - 1>([&](auto I) {
-      constexpr int i = I + 1;
-      in.template get_pull<i>(nbr.template get<i>(u), u, fr[i], fx[i]);
-    });
+    if constexpr (In::kPull) {
+      in.template get<0>(u, fr[0], fx[0]);
+      unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        in.template get_pull<i>(nbr.template get<i>(u), u, fr[i], fx[i]);
+      });
+    } else {
+      unroll<Q>([&](auto I) {
+        constexpr int i = I;
+        in.template get<i>(u, fr[i], fx[i]);
+      });
+    }
   } else {
     load_node<D>(in, nbr, n, fr, fx);
   }
