@@ -402,9 +402,13 @@ cg_status cg_lbm_drop_shape(cg_lbm* h, int base_axis, int wall_axis, int slice, 
  * (n_steps/K + K + 2) state copies (cg_info.state_bytes each) plus the adjoint
  * fields.  delta > 0 replaces |C| by max(|C|, delta) in the Jacobian of
  * n = C/|C| (Eq. 27) only; the forward arithmetic is unchanged; 0 keeps the
- * exact derivative.  Supported: closed and periodic boundaries with the body
- * force (CG_BC_NONE); CG_EUNSUPPORTED for Zou-He faces.  The handle's state
- * and step counter are left as they were.  Synchronises the stream. */
+ * exact derivative.  Every boundary of the step is covered: closed and
+ * periodic axes, the body force, and the Zou-He faces (Appendix B), whose
+ * runs also return the derivatives with respect to the inlet and outlet
+ * densities; an objective slab or plane may include the face layers (J then
+ * reads the face nodes' populations after the faces, as the next collision
+ * does).  The handle's state and step counter are left as they were.
+ * Synchronises the stream. */
 enum { CG_OBJ_SATURATION = 0, CG_OBJ_RED_VOLUME = 1, CG_OBJ_FLUX = 2 };
 
 typedef struct {
@@ -426,6 +430,8 @@ typedef struct {
   double ms_forward;         /* out: GPU time of the forward sweep */
   double ms_reverse;         /* out: GPU time of the reverse sweep, recomputation included */
   int64_t work_bytes;        /* out: device memory the call allocated */
+  double dJ_drho_in;         /* out: per unit of the Zou-He inlet density rho_in (0 without the faces) */
+  double dJ_drho_out;        /* out: per unit of the Zou-He outlet density rho_out (0 without the faces) */
 } cg_gradients;
 
 cg_status cg_lbm_adjoint(cg_lbm* h, const cg_adjoint_spec* spec, cg_gradients* out);

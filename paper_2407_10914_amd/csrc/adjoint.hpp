@@ -32,6 +32,23 @@
 //              boundary points
 //   ka_phi     the same at fluid nodes, the transpose of the phase
 //              extrapolation (Eq. 34), and phi = (rho^r - rho^b)/rho: writes R
+//   ka_face    (Zou-He runs) the transpose of the faces of Appendix B at the
+//              inlet and outlet nodes, which turns the adjoint of their
+//              post-face populations into the adjoint of the pulled ones
+//
+// Zou-He faces.  The state at a face node is the pulled populations; the
+// faces (Eqs. B.1-B.18) then set the unknown directions, so the node's own
+// reverse (ka_face_node) runs on the post-face populations and ka_face maps
+// the result back through the face.  At the inlet the face fixes both colour
+// densities (rho_in zeta^s), so the adjoint of every known pulled population
+// is the same for both colours and R is zero there.  At the outlet the
+// adjoint of a pulled population along +z is L_i + 2 R^s (the direction and
+// its reflected unknown both carry the node's density), in the plane L_i +
+// R^s; the reverse streaming applies that factor 2.  The outlet's chi^s and
+// its phase (Eq. 39) both come from the node upstream, whose density adjoint
+// receives their share.  The gradient stencils clamp at the open faces (the
+// face layer stands in for the missing one), so their transposes mirror e_z
+// on the clamped links.
 #pragma once
 
 #include "kernels.hpp"
@@ -146,9 +163,35 @@ struct AdjBufs {
   Real* lphi;          // [V] lambda phi / (sum of link weights) at solid boundary points, 0 elsewhere
   const Real* iden;    // [V] 1 / (sum of fluid-link weights) at solid boundary points, 0 elsewhere
   const double* idf;   // [Np] 1 / (sum of solid-link weights) at fluid boundary points, 0 elsewhere
-  double* pacc;        // [blocks][4] per-block sums over steps of lambda F (xyz) and lambda theta (per degree)
+  double* pacc;        // [blocks][kPaccCols] per-block sums over steps of lambda F (xyz), lambda theta
+                       // (per degree), lambda rho_in, lambda rho_out
   double* lth;         // [V] sum over steps of lambda theta * idf at fluid boundary voxels
+  Real* lpo;           // [n_out] lambda phi of each outlet node (its phase is the node's upstream, Eq. 39)
+  int face_pull;       // the state of this step is a pulled one (the faces were applied to it)
 };
+
+// Columns of the per-block parameter sums.
+constexpr int kPaccCols = 6;
+constexpr int kColTheta = 3, kColRhoIn = 4, kColRhoOut = 5;
+
+// A link of p whose z step is clamped at an open face: the forward gradient
+// stencils read the face layer itself there (zero-gradient ghost), so in
+// their transposes the relation runs within the layer, with e_z mirrored.
+// Only the z faces can be open; walls bound the other axes (a fluid node
+// never clamps there, and the solid voxels it would reach hold no adjoint).
+template <int D, int j>
+__device__ __forceinline__ bool clamped_z(const StepParams& P, const Pos& p) {
+  if constexpr (D != 3) {
+    return false;
+  } else {
+    constexpr int ez = Lat<D>::e(j, 2);
+    if constexpr (ez == 0) {
+      return false;
+    } else {
+      return p.face && P.per[2] == 0 && (ez < 0 ? p.z == 0 : p.z == P.nz - 1);
+    }
+  }
+}
 
 __device__ __forceinline__ int coord_of(const StepParams& P, int v, int axis) {
   const int nxy = P.nx * P.ny;
@@ -161,14 +204,13 @@ __device__ __forceinline__ void nbr_all(const Geo<Real>& G, int n, int* src) {
   G.nbr.template all<Lat<D>::Q>(n, src);
 }
 
-// Populations of node n of the state `in` as canonical red and total values
-// (double for the FP64 state; the compact FP32 state keeps g = f^t - w rho0).
-template <class Real, int D, class In>
-__device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G, const In& in, int n, Real* fr,
-                                         Real* fx, Real& rr, Real& rb, Real& rho) {
+// Colour densities of populations fr (red) and fx (blue for the FP64 state;
+// g = f^t - w rho0 for the compact FP32 state).
+template <class Real, int D>
+__device__ __forceinline__ void adj_sums(const StepParams& P, const Real* fr, const Real* fx, Real& rr, Real& rb,
+                                         Real& rho) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
-  load_node<D>(in, G.nbr, n, fr, fx);
   Real a = fr[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) a = a + fr[i];
@@ -190,6 +232,32 @@ __device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G
   }
 }
 
+// Pulled populations of node n of the state `in` and their colour densities.
+template <class Real, int D, class In>
+__device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G, const In& in, int n, Real* fr,
+                                         Real* fx, Real& rr, Real& rb, Real& rho) {
+  load_node<D>(in, G.nbr, n, fr, fx);
+  adj_sums<Real, D>(P, fr, fx, rr, rb, rho);
+}
+
+// The same with the Zou-He faces applied at a face node of a pulled state
+// (Appendix B): the populations the collision of the next step takes, and
+// the state as the oracle holds it.  The outlet's stored phase is the
+// upstream node's (Eq. 39), set by the phase stages of this state.
+template <class Real, int D, class In>
+__device__ __forceinline__ void adj_load_faced(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
+                                               const In& in, int n, Real* fr, Real* fx, Real& rr, Real& rb,
+                                               Real& rho) {
+  load_node<D>(in, G.nbr, n, fr, fx);
+  if constexpr (D == 3 && In::kPull) {
+    const unsigned vf = G.vf[n];
+    const unsigned fl = flags_of(vf);
+    if (fl & (FL_IN | FL_OUT))
+      zou_he<sizeof(Real) == 4>(P, fl, (Real)phi_dec(R.phi[vox_of(vf)]), fr, fx);
+  }
+  adj_sums<Real, D>(P, fr, fx, rr, rb, rho);
+}
+
 // ------------------------------------------------------------------ ka_node
 // Streaming form, three passes over the directions so that few per-direction
 // values stay live:
@@ -205,17 +273,30 @@ __device__ __forceinline__ void adj_load(const StepParams& P, const Geo<Real>& G
 //   pass 3  lambda f_i += e_i . lambda j (velocity, Eq. 22), store L.
 // kSeed: no lambda_{t+1}; the plane-flux objective J = sum (j + F/2)_axis is
 // seeded at the plane nodes instead (terminal condition of objective 2).
+// kFaceMode, runs with Zou-He faces: 1, the reverse streaming reads
+// lambda_{t+1} in its face form (open links carry nothing, the outlet's +z
+// populations weigh R twice); 2, the state at t is a pulled one as well: the
+// face nodes are skipped here and done by the kFace instantiation, which
+// runs on their post-face populations.
 // lF receives this node's lambda F (summed per block by the caller).
-template <class Real, int D, bool kSeed, bool kMrt, class In>
+template <class Real, int D, bool kSeed, bool kMrt, int kFaceMode, bool kFace, class In>
 __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
                                            const In& in, const AdjBufs<Real>& A, const AdjParams& AP, int n,
                                            double* lFout) {
   static_assert(D == 3 || !kMrt, "MRT is defined for D3Q19");
+  static_assert(kFaceMode == 0 || D == 3, "the faces are those of D3Q19 runs");
+  static_assert(kFaceMode < 2 || In::kPull, "the faces act on pulled states");
+  static_assert(kFaceMode == 2 || !kFace, "face nodes are handled apart for pulled states only");
+  constexpr bool kFaces = kFaceMode >= 1;
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = Real;
   const unsigned vf = G.vf[n];
   const int v = vox_of(vf);
+  const unsigned fl = flags_of(vf);
+  if constexpr (kFaceMode == 2 && !kFace) {
+    if (fl & (FL_IN | FL_OUT)) return;
+  }
   const CT rho0 = (CT)P.rho0;
   // pull-table entries of the node (the reverse streaming uses them too)
   int src[Q];
@@ -226,7 +307,17 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   CT x[Q];
   CT rr, rb, rho, drho;
   if constexpr (kDev) {
-    if constexpr (In::kPull) {
+    if constexpr (kFace) {
+      // per-colour pull with the faces applied, as the step kernel takes
+      // them; rho^r is the post-face red sum (the node's phase is not its own)
+      Real fr[Q];
+      load_node<D>(in, G.nbr, n, fr, x);
+      zou_he<true>(P, fl, (Real)phi_dec(R.phi[v]), fr, x);
+      CT a = fr[0];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) a = a + fr[i];
+      rr = a;
+    } else if constexpr (In::kPull) {
       unroll<Q>([&](auto I) {
         constexpr int i = I;
         if constexpr (i == 0) {
@@ -237,12 +328,18 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
         }
       });
     } else {
+      // a state set at the nodes holds the red populations themselves: rho^r
+      // is their sum, as the step takes it (at the face nodes the stored
+      // phase is not the node's own ratio)
+      CT a = CT(0);
       unroll<Q>([&](auto I) {
         constexpr int i = I;
         CT r, g;
         in.template get<i>(n, r, g);
         x[i] = g;
+        a = a + r;
       });
+      rr = a;
     }
     CT t = (CT)Lat<D>::w(0) * rho0 + x[0];
     CT sg = x[0];
@@ -253,11 +350,12 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     });
     rho = t;
     drho = sg;
-    rr = rho * (CT(1) + (CT)phi_dec(R.phi[v])) * CT(0.5);
+    if constexpr (!kFace && In::kPull) rr = rho * (CT(1) + (CT)phi_dec(R.phi[v])) * CT(0.5);
     rb = rho - rr;
   } else {
     Real fr[Q], fx[Q];
     load_node<D>(in, G.nbr, n, fr, fx);
+    if constexpr (kFace) zou_he<false>(P, fl, (Real)phi_dec(R.phi[v]), fr, fx);
     CT a = fr[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) a = a + (CT)fr[i];
@@ -364,6 +462,10 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     CT dl = CT(0), m = CT(0);
     if constexpr (!kSeed) {
       int li, ri;
+      // open: c_i leaves through an open face; zf: the pulled population it
+      // becomes is a +z one of an outlet node (adjoint L + 2 R^s there)
+      [[maybe_unused]] bool open = false;
+      CT zf = CT(1);
       if constexpr (i == 0) {
         li = n;
         ri = n;
@@ -376,11 +478,23 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
         // into branches that wait for earlier loads
         asm("" : "+v"(ri), "+v"(row));
         li = row + ri;
+        if constexpr (kFaces) {
+          constexpr int ez = Lat<D>::e(i, 2);
+          open = s < kBounce;
+          if constexpr (ez != 0) {
+            const bool up = ez > 0 ? s >= 0 : s == kBounce;
+            zf = (up && ri >= P.N - P.n_out) ? CT(2) : CT(1);
+          }
+        }
       }
       const CT l = A.lf_in[li];
       const Vec2<Real> r = A.lr[ri];
-      dl = (CT)r.x - (CT)r.y;
-      m = l + (CT)r.y + ra * dl;
+      dl = zf * ((CT)r.x - (CT)r.y);
+      m = l + zf * (CT)r.y + ra * dl;
+      if constexpr (kFaces) {
+        dl = open ? CT(0) : dl;
+        m = open ? CT(0) : m;
+      }
     }
     a1 = a1 + bg[i] * dl;
     if constexpr (kMrt) {
@@ -570,15 +684,24 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   lrho = lrho - (la * ra + lb * rbb) * irho;
   lrr = lrr + lrho;
   lrb = lrb + lrho;
-  // phi = (rho^r - rho^b) / rho
-  const CT dr = CT(2) * rb * irho * irho;
-  const CT db = CT(-2) * rr * irho * irho;
+  // phi = (rho^r - rho^b) / rho, except at an inlet node (phi_in) and an
+  // outlet node (the upstream node's phase, Eq. 39): their lambda phi does
+  // not reach their own densities; the outlet's goes to the node upstream
+  // (ka_face; not needed for the first step of the call, whose adjoint is
+  // not used)
+  bool own = true;
+  if constexpr (D == 3) own = !(fl & (FL_IN | FL_OUT));
+  const CT dr = own ? CT(2) * rb * irho * irho : CT(0);
+  const CT db = own ? CT(-2) * rr * irho * irho : CT(0);
   Vec4<Real> na;
   na.x = lrr + lsnu * dr;
   na.y = lrb + lsnu * db;
   na.z = dr;
   na.w = db;
   A.na[n] = na;
+  if constexpr (kFace) {
+    if (fl & FL_OUT) A.lpo[n - (P.N - P.n_out)] = lsnu;
+  }
   // force F = sigma/2 kappa C + rho0 g
   const Vec4<Real> c4 = n_get(R.c, n);
   const CT Cv[3] = {(CT)c4.x, (CT)c4.y, (CT)c4.z};
@@ -611,19 +734,30 @@ __device__ __forceinline__ void block_accumulate(const double* vals, int col0, d
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double t = block_sum<BS>(vals[c], sh);
-    if (threadIdx.x == 0) pacc[blockIdx.x * 4 + col0 + c] += t;
+    if (threadIdx.x == 0) pacc[blockIdx.x * kPaccCols + col0 + c] += t;
   }
 }
 
 // Three waves per SIMD: without the hint the compiler keeps every gather of
 // the node in flight in 221 VGPRs (two waves); with it 158 VGPRs, no spills
 // (four waves would spill).
-template <class Real, int D, bool kSeed, bool kMrt, class In>
+template <class Real, int D, bool kSeed, bool kMrt, int kFaceMode, class In>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 ka_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A, AdjParams AP) {
   const int n = node_id_plain();
   double lF[3] = {0.0, 0.0, 0.0};
-  if (n < P.N) d_adj_node<Real, D, kSeed, kMrt, In>(P, G, R, in, A, AP, n, lF);
+  if (n < P.N) d_adj_node<Real, D, kSeed, kMrt, kFaceMode, false, In>(P, G, R, in, A, AP, n, lF);
+  block_accumulate<256, 3>(lF, 0, A.pacc);
+}
+
+// The same at the Zou-He face nodes of a pulled state, one wave per 64-node
+// tile that holds face nodes (the pull table decodes per tile).
+template <class Real, int D, bool kSeed, bool kMrt, class In>
+__global__ void __launch_bounds__(256)
+ka_face_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A, AdjParams AP) {
+  const int n = face_node(P, node_id_plain());
+  double lF[3] = {0.0, 0.0, 0.0};
+  if (n >= 0) d_adj_node<Real, D, kSeed, kMrt, 2, true, In>(P, G, R, in, A, AP, n, lF);
   block_accumulate<256, 3>(lF, 0, A.pacc);
 }
 
@@ -631,7 +765,9 @@ ka_node(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjBufs<Real> A, AdjPar
 // kappa(x) = sum_ab (n_a n_b - delta_ab) d_b n_a with d_b n_a = 3 sum_i w_i e_ib n_a(x + e_i):
 //   at y = x + e_i: lambda n_a(y) += 3 w_i lambda kappa(x) (n_a(x) (e_i.n(x)) - e_ia)
 //   at x itself:    lambda n_a(x) += lambda kappa(x) sum_b (d_b n_a + d_a n_b) n_b
-// Written as a gather at y over x = y + e_j (e_j = -e_i).
+// Written as a gather at y over x = y + e_j (e_j = -e_i); on a link clamped
+// at an open face x lies in y's layer and e_j enters mirrored in z (the own
+// stencil d keeps e_j: it is y's forward stencil).
 template <class Real, int D, bool kSb>
 __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>& G, const Grids<Real>& R,
                                            const AdjBufs<Real>& A, int idx) {
@@ -668,10 +804,11 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
     constexpr int j = J + 1;
     constexpr double w = Lat<D>::w(j);
     const int x = nbi[j];
+    const bool cl = clamped_z<D, j>(P, ps);
     Vec4<Real> q;
     CT lk;
     if constexpr (kSb) {
-      const bool on = msk & (1u << j);
+      const bool on = (msk & (1u << j)) || cl;
       q = bload3<Real>(rn, on ? (uint32_t)x * (uint32_t)sizeof(Norm3<Real>) : kOffNone);
       lk = bload1(rk, on ? (uint32_t)x * (uint32_t)sizeof(Real) : kOffNone, Real(0));
     } else {
@@ -679,18 +816,22 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
       lk = (CT)A.lk[x];
     }
     const CT nq[3] = {(CT)q.x, (CT)q.y, (CT)q.z};
+    // e_j, mirrored in z on a clamped link
+    CT ej[3];
+    unroll<D>([&](auto A_) {
+      constexpr int a = A_;
+      constexpr CT e = (CT)Lat<D>::e(j, a);
+      ej[a] = (a == 2 && cl) ? -e : e;
+    });
     CT en = CT(0);
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
-      constexpr int e = Lat<D>::e(j, a);
-      if constexpr (e == 1) en = en + nq[a];
-      if constexpr (e == -1) en = en - nq[a];
+      en = en + ej[a] * nq[a];
     });
     const CT c = (CT)(3.0 * w) * lk;
     unroll<D>([&](auto A_) {
       constexpr int a = A_;
-      constexpr CT e = (CT)Lat<D>::e(j, a);
-      acc[a] = acc[a] + c * (e - nq[a] * en);
+      acc[a] = acc[a] + c * (ej[a] - nq[a] * en);
     });
     if constexpr (!kSb) {
       unroll<D>([&](auto B_) {
@@ -764,7 +905,8 @@ __device__ __forceinline__ void d_adj_normal(const StepParams& P, const Geo<Real
       const int x = nbi[j];
       const Real id = A.iden[x];
       const Vec4<Real> q = A.ln[x];
-      const CT c = (CT)Lat<D>::w(j) * (CT)id;
+      // (the points' links are unclamped)
+      const CT c = clamped_z<D, j>(P, ps) ? CT(0) : (CT)Lat<D>::w(j) * (CT)id;
       ln[0] = ln[0] + c * (CT)q.x;
       ln[1] = ln[1] + c * (CT)q.y;
       if constexpr (D == 3) ln[2] = ln[2] + c * (CT)q.z;
@@ -853,26 +995,40 @@ __global__ void __launch_bounds__(256) ka_normal(StepParams P, Geo<Real> G, Grid
   const int n = node_id_plain();
   double lth = 0.0;
   if (n < P.N) d_adj_normal<Real, D>(P, G, R, A, AP, n, &lth);
-  block_accumulate<256, 1>(&lth, 3, A.pacc);
+  block_accumulate<256, 1>(&lth, kColTheta, A.pacc);
 }
 
 // ------------------------------------------------------- ka_sb_phi, ka_phi
 // C(x) = 3 sum_i w_i e_i phi(x + e_i)  =>  lambda phi(y) = -3 sum_j w_j e_j . lambda C(y + e_j)
+// On a link clamped at an open face the node x = y + (e_j with no z step)
+// reads y along the direction e_j mirrored in z, so e_z changes sign there.
+template <int D, int j, class Real>
+__device__ __forceinline__ Real grad_t_term(const Real* qq, bool mirror) {
+  Real t = Real(0);
+  unroll<D>([&](auto A_) {
+    constexpr int a = A_;
+    constexpr int e = Lat<D>::e(j, a);
+    if constexpr (a < 2) {
+      if constexpr (e == 1) t = t + qq[a];
+      if constexpr (e == -1) t = t - qq[a];
+    } else if constexpr (e != 0) {
+      const Real z = e == 1 ? qq[2] : -qq[2];
+      t = t + (mirror ? -z : z);
+    }
+  });
+  return t;
+}
+
 template <class Real, int D>
-__device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Real>& A, const int* nbi) {
+__device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Real>& A, const Pos& ps,
+                                           const int* nbi) {
   constexpr int Q = Lat<D>::Q;
   Real acc = Real(0);
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
     const Vec4<Real> q = A.lc[nbi[j]];
     const Real qq[3] = {q.x, q.y, q.z};
-    Real t = Real(0);
-    unroll<D>([&](auto A_) {
-      constexpr int a = A_;
-      constexpr int e = Lat<D>::e(j, a);
-      if constexpr (e == 1) t = t + qq[a];
-      if constexpr (e == -1) t = t - qq[a];
-    });
+    const Real t = grad_t_term<D, j>(qq, clamped_z<D, j>(P, ps));
     acc = acc + (Real)(-3.0 * Lat<D>::w(j)) * t;
   });
   return acc;
@@ -881,25 +1037,23 @@ __device__ __forceinline__ Real adj_grad_t(const StepParams& P, const AdjBufs<Re
 // The same at a solid boundary point, over its fluid links only: lambda C is
 // written on fluid voxels alone (zero elsewhere), so the skipped terms are
 // exact zeros; masked buffer loads keep every gather in flight together.
+// (The links of a point's mask are unclamped; in a face layer the fluid
+// nodes of the layer that read the point through a clamped link are
+// gathered as well.)
 template <class Real, int D>
-__device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs<Real>& A, const int* nbi,
-                                              unsigned msk) {
+__device__ __forceinline__ Real adj_grad_t_sb(const StepParams& P, const AdjBufs<Real>& A, const Pos& ps,
+                                              const int* nbi, unsigned msk) {
   constexpr int Q = Lat<D>::Q;
   const auto rc = grid_rsrc(A.lc, sizeof(Vec4<Real>) * (size_t)P.V);
   Real acc = Real(0);
   unroll<Q - 1>([&](auto J) {
     constexpr int j = J + 1;
-    const bool on = msk & (1u << j);
+    const bool cl = clamped_z<D, j>(P, ps);
+    const bool on = (msk & (1u << j)) || cl;
     const Vec4<Real> q =
         bload3<Real>(rc, on ? (uint32_t)nbi[j] * (uint32_t)sizeof(Vec4<Real>) : kOffNone);
     const Real qq[3] = {q.x, q.y, q.z};
-    Real t = Real(0);
-    unroll<D>([&](auto A_) {
-      constexpr int a = A_;
-      constexpr int e = Lat<D>::e(j, a);
-      if constexpr (e == 1) t = t + qq[a];
-      if constexpr (e == -1) t = t - qq[a];
-    });
+    const Real t = grad_t_term<D, j>(qq, cl);
     acc = acc + (Real)(-3.0 * Lat<D>::w(j)) * t;
   });
   return acc;
@@ -920,13 +1074,13 @@ __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
       const Pos ps = make_pos(P, v, m & 1u);
       int nbi[Lat<D>::Q];
       nb_all<D>(P, ps, nbi);
-      const double lp = (double)adj_grad_t_sb<Real, D>(P, A, nbi, m);
+      const double lp = (double)adj_grad_t_sb<Real, D>(P, A, ps, nbi, m);
       const double c = (double)G.sb_fd[s];
       lth = lp * ::sqrt(::fmax(0.0, 1.0 - c * c)) * (M_PI / 180.0);
       A.lphi[v] = Real(0);
       A.lth[v] += lth;
     }
-    block_accumulate<256, 1>(&lth, 3, A.pacc);
+    block_accumulate<256, 1>(&lth, kColTheta, A.pacc);
     return;
   }
   if (s >= P.nsb) return;
@@ -935,7 +1089,7 @@ __global__ void ka_sb_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   const Pos ps = make_pos(P, v, m & 1u);
   int nbi[Lat<D>::Q];
   nb_all<D>(P, ps, nbi);
-  A.lphi[v] = adj_grad_t_sb<Real, D>(P, A, nbi, m) * A.iden[v];
+  A.lphi[v] = adj_grad_t_sb<Real, D>(P, A, ps, nbi, m) * A.iden[v];
 }
 
 template <class Real, int D>
@@ -948,12 +1102,14 @@ __global__ void ka_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   const Pos ps = make_pos(P, v, flags_of(vf) & FL_FACE);
   int nbi[Q];
   nb_all<D>(P, ps, nbi);
-  Real lp = adj_grad_t<Real, D>(P, A, nbi);
+  Real lp = adj_grad_t<Real, D>(P, A, ps, nbi);
   if (A.idf[n] != 0.0) {
     // transpose of Eq. (34): phi(s) = sum_i w_i phi(s + e_i) / sum_i w_i
+    // over the point's (unclamped) links
     unroll<Q - 1>([&](auto J) {
       constexpr int j = J + 1;
-      lp = lp + (Real)Lat<D>::w(j) * A.lphi[nbi[j]];
+      const Real w = clamped_z<D, j>(P, ps) ? Real(0) : (Real)Lat<D>::w(j);
+      lp = lp + w * A.lphi[nbi[j]];
     });
   }
   const Vec4<Real> na = A.na[n];
@@ -961,6 +1117,9 @@ __global__ void ka_phi(StepParams P, Geo<Real> G, AdjBufs<Real> A) {
   r.x = na.x + lp * na.z;
   r.y = na.y + lp * na.w;
   A.lr[n] = r;
+  // the phase of an outlet node of a pulled state is the upstream node's
+  // (Eq. 39): its lambda phi is handed on by ka_face
+  if (A.face_pull && (flags_of(vf) & FL_OUT)) A.lpo[n - (P.N - P.n_out)] += lp;
 }
 
 // -------------------------------------------------------- objective, seeds
@@ -979,7 +1138,7 @@ __global__ void __launch_bounds__(BS) ka_obj(StepParams P, Geo<Real> G, Grids<Re
     const int v = vox_of(G.vf[n]);
     const int c = coord_of(P, v, AP.axis);
     Real fr[Q], fx[Q], rr, rb, rho;
-    adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+    adj_load_faced<Real, D>(P, G, R, in, n, fr, fx, rr, rb, rho);
     if (c >= AP.lo && c < AP.hi) {
       o[0] = (double)rr;
       o[1] = (double)rb;
@@ -1029,8 +1188,8 @@ __global__ void ka_reduce(const double* part, int nb, int nq, double* out) {
 // saturation J = S_r / (S_r + S_b): dJ/drho^r = S_b / S^2, dJ/drho^b = -S_r / S^2;
 // red volume J = sum (1 + phi)/2: dJ/drho^r = rho^b / rho^2, dJ/drho^b = -rho^r / rho^2.
 template <class Real, int D, class In>
-__global__ void ka_seed_local(StepParams P, Geo<Real> G, In in, AdjParams AP, const double* sums, Real* lf,
-                              Vec2<Real>* lr) {
+__global__ void ka_seed_local(StepParams P, Geo<Real> G, Grids<Real> R, In in, AdjParams AP, const double* sums,
+                              Real* lf, Vec2<Real>* lr) {
   constexpr int Q = Lat<D>::Q;
   const int n = node_id_plain();
   if (n >= P.N) return;
@@ -1044,7 +1203,7 @@ __global__ void ka_seed_local(StepParams P, Geo<Real> G, In in, AdjParams AP, co
       gb = -sums[0] / (S * S);
     } else {
       Real fr[Q], fx[Q], rr, rb, rho;
-      adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+      adj_load_faced<Real, D>(P, G, R, in, n, fr, fx, rr, rb, rho);
       const double ir = 1.0 / (double)rho;
       gr = (double)rb * ir * ir;
       gb = -(double)rr * ir * ir;
@@ -1056,6 +1215,119 @@ __global__ void ka_seed_local(StepParams P, Geo<Real> G, In in, AdjParams AP, co
   r.x = (Real)gr;
   r.y = (Real)gb;
   lr[n] = r;
+}
+
+// ------------------------------------------------------------------ ka_face
+// Transpose of the Zou-He faces (Appendix B) at each face node x of a pulled
+// state.  On entry L (the total part) and R = (R^r, R^b) are the adjoint of
+// x's post-face populations, lambda^s_i = L_i + R^s; on exit L holds the
+// known pulled directions, with R as the reverse streaming reads it (inlet:
+// R = 0; outlet: weight 2 along +z).  With the per-colour unknowns of the
+// faces written as f_u = f_k(u) + c_u j^s +- N^s (B.4-B.8, B.14-B.18):
+//   inlet,  j^s = rho_in zeta^s - (S^s + 2 T^s):  lambda_j^s = lambda_j^L + R^s
+//           (the five unknowns carry weights 1/3 + 4/6 = 1), the R^s
+//           cancel on every known direction;
+//   outlet, j^s = chi^s j^t, j^t = (S^t + 2 T^t) - rho_out:
+//           lambda_j^s = lambda_j^L - R^s, lambda j^t = lambda_j^L - sum_s chi^s R^s,
+//           lambda phi_up += j^t (R^b - R^r) / 2 from chi^s = (1 +- phi_up)/2,
+//           and phi_up (with the outlet node's own lambda phi, Eq. 39)
+//           passes to the upstream node's densities.
+// The node also adds its shares of dJ/drho_in and dJ/drho_out.
+template <class Real, int D, class In>
+__global__ void __launch_bounds__(256) ka_face(StepParams P, Geo<Real> G, Grids<Real> R, In in, Real* L,
+                                               Vec2<Real>* lr, const Real* lpo, double* pacc) {
+  constexpr int Q = Lat<D>::Q;
+  constexpr bool kDev = sizeof(Real) == 4;
+  using CT = Real;
+  const int n = face_node(P, node_id_plain());
+  double g[2] = {0.0, 0.0};
+  if constexpr (D == 3) {
+    if (n >= 0) {
+      const unsigned vf = G.vf[n];
+      const unsigned fl = flags_of(vf);
+      const bool inl = fl & FL_IN;
+      CT l[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) l[i] = L[i * P.Np + n];
+      const Vec2<Real> r = lr[n];
+      const CT Rr = (CT)r.x, Rb = (CT)r.y;
+      // sums over the known directions: S in the plane, T the directions
+      // leaving through the face (their unknowns are their reflections)
+      constexpr int kS[9] = {0, 1, 2, 3, 4, 7, 8, 9, 10};
+      CT o[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) o[i] = CT(0);
+      CT lj, lnx, lny, lam = CT(0);
+      if (inl) {
+        lj = l[5] / CT(3) + (l[11] + l[12] + l[15] + l[16]) / CT(6);
+        lnx = l[12] - l[11];
+        lny = l[16] - l[15];
+        lam = -lj;  // d j / d f_k = -1 (S), -2 (T)
+      } else {
+        lj = -l[6] / CT(3) - (l[13] + l[14] + l[17] + l[18]) / CT(6);
+        lnx = l[14] - l[13];
+        lny = l[18] - l[17];
+        const CT phu = (CT)phi_dec(R.phi[vox_of(vf)]);
+        const CT chr = CT(0.5) * (CT(1) + phu), chb = CT(0.5) * (CT(1) - phu);
+        lam = lj - (chr * Rr + chb * Rb);  // lambda j^t; d j^t / d f_k = +1 (S), +2 (T)
+        g[1] = -(double)lam;               // d j^t / d rho_out = -1
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) o[kS[k]] = l[kS[k]] + lam;
+      // Nx = (f1 + f7 + f9 - f2 - f8 - f10)/2, Ny = (f3 + f7 + f8 - f4 - f9 - f10)/2
+      const CT hx = CT(0.5) * lnx, hy = CT(0.5) * lny;
+      o[1] = o[1] + hx;
+      o[2] = o[2] - hx;
+      o[3] = o[3] + hy;
+      o[4] = o[4] - hy;
+      o[7] = o[7] + hx + hy;
+      o[8] = o[8] - hx + hy;
+      o[9] = o[9] + hx - hy;
+      o[10] = o[10] - hx - hy;
+      if (inl) {
+        // known T = {6, 13, 14, 17, 18}; unknowns 5 <- 6, 11 <- 14, 12 <- 13, 15 <- 18, 16 <- 17
+        o[6] = l[6] + CT(2) * lam + l[5];
+        o[13] = l[13] + CT(2) * lam + l[12];
+        o[14] = l[14] + CT(2) * lam + l[11];
+        o[17] = l[17] + CT(2) * lam + l[16];
+        o[18] = l[18] + CT(2) * lam + l[15];
+        const double zr = P.zeta_r;
+        g[0] = (double)lj + zr * (double)Rr + (1.0 - zr) * (double)Rb;
+        Vec2<Real> z0;
+        z0.x = Real(0);
+        z0.y = Real(0);
+        lr[n] = z0;
+      } else {
+        // known T = {5, 11, 12, 15, 16}; unknowns 6 <- 5, 13 <- 12, 14 <- 11, 17 <- 16, 18 <- 15
+        o[5] = l[5] + CT(2) * lam + l[6];
+        o[12] = l[12] + CT(2) * lam + l[13];
+        o[11] = l[11] + CT(2) * lam + l[14];
+        o[16] = l[16] + CT(2) * lam + l[17];
+        o[15] = l[15] + CT(2) * lam + l[18];
+        // j^t from the pulled totals of x, and the upstream node's densities
+        Real fr[Q], fx[Q], rr, rb, rho;
+        adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+        CT ft[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) ft[i] = kDev ? fx[i] : fr[i] + fx[i];
+        const CT S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
+        const CT T = ft[5] + ft[11] + ft[12] + ft[15] + ft[16];
+        const CT jt = -(CT)(kDev ? P.rho_out - P.rho0 : P.rho_out) + (S + CT(2) * T);
+        const CT lphu = lpo[n - (P.N - P.n_out)] + CT(0.5) * jt * (Rb - Rr);
+        const int u = G.nbr.template get<kDirZp>(n);
+        load_outlet_upstream<D>(in, G.nbr, n, fr, fx);
+        adj_sums<Real, D>(P, fr, fx, rr, rb, rho);
+        const CT ir = CT(1) / rho;
+        Vec2<Real> ru = lr[u];
+        ru.x = ru.x + lphu * (CT(2) * rb * ir * ir);
+        ru.y = ru.y + lphu * (CT(-2) * rr * ir * ir);
+        lr[u] = ru;
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) L[i * P.Np + n] = o[i];
+    }
+  }
+  block_accumulate<256, 2>(g, kColRhoIn, pacc);
 }
 
 // ------------------------------------------------------------ setup, output

@@ -28,11 +28,6 @@ class AdjointRun {
   }
 
   int run(const cg_adjoint_spec& sp, cg_gradients* g) {
-    const StepParams& P = E.P_;
-    if (P.bc != 0) {
-      E.err_ = "the adjoint covers closed and periodic boundaries with the body force (no Zou-He faces)";
-      return CG_EUNSUPPORTED;
-    }
     if (sp.n_steps < 1 || sp.checkpoint_every < 1) {
       E.err_ = "n_steps and checkpoint_every must be >= 1";
       return CG_EINVAL;
@@ -67,6 +62,8 @@ class AdjointRun {
   double *idf_ = nullptr, *lth_ = nullptr, *part_ = nullptr, *sums_ = nullptr;
   double* pacc_ = nullptr;
   int npacc_ = 0;  // rows of pacc_
+  Real* lpo_ = nullptr;  // lambda phi of the outlet nodes (Zou-He runs)
+  int face_pull_ = 0;    // the state of the current step is pulled and has face nodes
   // front fields (phase, normal, colour gradient, force) of the state at
   // t0 + k for each ring index k, kept from the recomputation so the reverse
   // step does not evaluate the front stages again; empty when the memory was
@@ -113,7 +110,8 @@ class AdjointRun {
     return e;
   }
   AdjBufs<Real> bufs() const {
-    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_, na_, lcf_, lk_, ln_, lc_, lphi_, iden_, idf_, pacc_, lth_};
+    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_,   na_,  lcf_,  lk_, ln_,
+                         lc_,     lphi_,       iden_, idf_, pacc_, lth_, lpo_, face_pull_};
   }
 
   // one forward step from `in` into slot `out`; the front fields go to the
@@ -145,9 +143,62 @@ class AdjointRun {
     p_ ^= 1;
   }
 
-  // lambda_{t} from lambda_{t+1}, the state at t being `in` (ring index k)
+  // Zou-He runs: whether the state `in` is a pulled one (the faces act on it)
   template <int D, class In>
-  void rstep(const In& in, int64_t k) {
+  bool faces_of(const In&) const {
+    return D == 3 && In::kPull && E.P_.n_in + E.P_.n_out > 0;
+  }
+  // the node stage; with Zou-He faces the reverse streaming reads the face
+  // form of lambda_{t+1}, and the face nodes of a pulled state go apart
+  template <int D, bool kSeed, class In>
+  void node_stage(const In& in, const Grids<Real>& R) {
+    const StepParams& P = E.P_;
+    if constexpr (D == 3) {
+      if (P.n_in + P.n_out > 0) {
+        constexpr int kMode = In::kPull ? 2 : 1;
+        if (P.collision == 1)
+          E.launch(-1, ka_node<Real, D, kSeed, true, kMode, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+        else
+          E.launch(-1, ka_node<Real, D, kSeed, false, kMode, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+        if constexpr (In::kPull) face_nodes<D, kSeed>(in, R);
+        return;
+      }
+      if (P.collision == 1)
+        E.launch(-1, ka_node<Real, D, kSeed, true, 0, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+      else
+        E.launch(-1, ka_node<Real, D, kSeed, false, 0, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+    } else {
+      E.launch(-1, ka_node<Real, D, kSeed, false, 0, In>, P.N, P, E.G_, R, in, bufs(), AP_);
+    }
+  }
+  // the node stage at the face nodes of a pulled state (after ka_node,
+  // which skips them)
+  template <int D, bool kSeed, class In>
+  void face_nodes(const In& in, const Grids<Real>& R) {
+    const StepParams& P = E.P_;
+    if constexpr (D == 3 && In::kPull) {
+      const int nt = 64 * face_tiles(P);
+      if (P.collision == 1)
+        E.launch(-1, ka_face_node<Real, D, kSeed, true, In>, nt, P, E.G_, R, in, bufs(), AP_);
+      else
+        E.launch(-1, ka_face_node<Real, D, kSeed, false, In>, nt, P, E.G_, R, in, bufs(), AP_);
+    }
+  }
+  // the transpose of the faces on the adjoint just formed (lf_[p_], lr_)
+  template <int D, class In>
+  void face_transpose(const In& in, const Grids<Real>& R) {
+    const StepParams& P = E.P_;
+    if constexpr (D == 3 && In::kPull)
+      E.launch(-1, ka_face<Real, D, In>, 64 * face_tiles(P), P, E.G_, R, in, lf_[p_], lr_, (const Real*)lpo_,
+               pacc_);
+  }
+
+  // lambda_{t} from lambda_{t+1}, the state at t being `in` (ring index k).
+  // first: t is the first step of the call, whose state is held fixed as
+  // it stands (after the faces, as the oracle holds a state): the faces that
+  // made it are not part of the map, and lambda_0 itself is not needed.
+  template <int D, class In>
+  void rstep(const In& in, int64_t k, bool first) {
     const StepParams& P = E.P_;
     Grids<Real> R = E.R_;
     if (!fg_.empty()) {
@@ -155,15 +206,10 @@ class AdjointRun {
     } else {
       E.template front_with<D>(in, 5);
     }
-    if constexpr (D == 3) {
-      if (P.collision == 1)
-        E.launch(-1, ka_node<Real, D, false, true, In>, P.N, P, E.G_, R, in, bufs(), AP_);
-      else
-        E.launch(-1, ka_node<Real, D, false, false, In>, P.N, P, E.G_, R, in, bufs(), AP_);
-    } else {
-      E.launch(-1, ka_node<Real, D, false, false, In>, P.N, P, E.G_, R, in, bufs(), AP_);
-    }
+    face_pull_ = faces_of<D>(in) ? 1 : 0;
+    node_stage<D, false>(in, R);
     reverse_tail<D>(R);
+    if (face_pull_ && !first) face_transpose<D>(in, R);
   }
 
   // objective of the state `in` (into sums_) and the terminal adjoint
@@ -172,21 +218,19 @@ class AdjointRun {
     const StepParams& P = E.P_;
     E.template front_with<D>(in, 5);
     const int nb = (P.N + BS - 1) / BS;
+    face_pull_ = faces_of<D>(in) ? 1 : 0;
     E.launch(-1, ka_obj<Real, D, BS, In>, P.N, P, E.G_, E.R_, in, AP_, part_);
     hipLaunchKernelGGL(ka_reduce<Real>, dim3(kObjN), dim3(256), 0, E.stream_, (const double*)part_, nb, kObjN, sums_);
     if (AP_.objective == 2) {
-      if constexpr (D == 3) {
-        if (P.collision == 1)
-          E.launch(-1, ka_node<Real, D, true, true, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
-        else
-          E.launch(-1, ka_node<Real, D, true, false, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
-      } else {
-        E.launch(-1, ka_node<Real, D, true, false, In>, P.N, P, E.G_, E.R_, in, bufs(), AP_);
-      }
+      node_stage<D, true>(in, E.R_);
       reverse_tail<D>(E.R_);
     } else {
-      E.launch(-1, ka_seed_local<Real, D, In>, P.N, P, E.G_, in, AP_, (const double*)sums_, lf_[p_], lr_);
+      E.launch(-1, ka_seed_local<Real, D, In>, P.N, P, E.G_, E.R_, in, AP_, (const double*)sums_, lf_[p_], lr_);
+      // the objective does not read the outlet phase (Eq. 39): no lambda phi there
+      if (face_pull_ && P.n_out > 0)
+        E.launch(-1, ka_fill<Real, Real>, P.n_out, (size_t)P.n_out, lpo_, Real(0));
     }
+    if (face_pull_) face_transpose<D>(in, E.R_);
   }
 
   template <int D>
@@ -238,14 +282,16 @@ class AdjointRun {
     idf_ = (double*)get(sizeof(double) * Np);
     lth_ = (double*)get(sizeof(double) * V);
     const int nb = (P.N + BS - 1) / BS;
-    // parameter rows: one per block of the node kernels and of the solid
-    // boundary kernel (the fictitious-density angle adjoint)
-    npacc_ = std::max(nb, (P.nsb + BS - 1) / BS);
-    pacc_ = (double*)get(sizeof(double) * 4 * (size_t)npacc_);
+    // parameter rows: one per block of the node kernels, of the solid
+    // boundary kernel (the fictitious-density angle adjoint) and of the face
+    // kernels (whole 64-node tiles: at most N + 128 threads)
+    npacc_ = std::max(nb + 1, (P.nsb + BS - 1) / BS);
+    pacc_ = (double*)get(sizeof(double) * kPaccCols * (size_t)npacc_);
     part_ = (double*)get(sizeof(double) * 4 * (size_t)(nb + 1));
-    sums_ = (double*)get(sizeof(double) * 8);
+    sums_ = (double*)get(sizeof(double) * (kObjN + kPaccCols));
+    lpo_ = (Real*)get(sizeof(Real) * (size_t)std::max(1, P.n_out));
     ok = ok && lf_[0] && lf_[1] && lr_ && na_ && lcf_ && lk_ && ln_ && lc_ && lphi_ && iden_ && idf_ && lth_ &&
-         pacc_ && part_ && sums_;
+         pacc_ && part_ && sums_ && lpo_;
     if (!ok) {
       E.err_ = "device allocation for the adjoint failed";
       return CG_ENOMEM;
@@ -261,9 +307,10 @@ class AdjointRun {
     zero(lphi_, sizeof(Real) * V);
     zero(iden_, sizeof(Real) * V);
     zero(lth_, sizeof(double) * V);
-    zero(pacc_, sizeof(double) * 4 * (size_t)npacc_);
+    zero(pacc_, sizeof(double) * kPaccCols * (size_t)npacc_);
     zero(lr_, sizeof(V2) * Np);
-    zero(sums_, sizeof(double) * 8);
+    zero(sums_, sizeof(double) * (kObjN + kPaccCols));
+    zero(lpo_, sizeof(Real) * (size_t)std::max(1, P.n_out));
     // grid voxels that no stage writes (interior solid) are read as zeros
     for (auto& x : fg_) {
       if (e == hipSuccess) e = Engine<Real>::fill_phi_zero(x.phi, V, st);
@@ -344,18 +391,20 @@ class AdjointRun {
         for (int64_t k = 0; k < L; ++k)
           with_seg(c, k, [&](const auto& in) { fstep<D>(in, ring[(size_t)k], k); });
       }
-      for (int64_t k = L - 1; k >= 0; --k) with_seg(c, k, [&](const auto& in) { rstep<D>(in, k); });
+      for (int64_t k = L - 1; k >= 0; --k)
+        with_seg(c, k, [&](const auto& in) { rstep<D>(in, k, c == 0 && k == 0); });
     }
     (void)hipEventRecord(e2, st);
 
     // parameter gradients
-    hipLaunchKernelGGL(ka_reduce<Real>, dim3(4), dim3(256), 0, st, (const double*)pacc_, npacc_, 4, sums_ + 4);
+    hipLaunchKernelGGL(ka_reduce<Real>, dim3(kPaccCols), dim3(256), 0, st, (const double*)pacc_, npacc_, kPaccCols,
+                       sums_ + kObjN);
     if (g->dJ_dtheta_field) {
       const size_t nbv = (V + 255) / 256;
       hipLaunchKernelGGL((ka_fill<Real, double>), dim3((unsigned)nbv), dim3(256), 0, st, V, g->dJ_dtheta_field, 0.0);
       if (P.nsb) E.launch(-1, ka_theta_field<Real, D>, P.nsb, P, E.G_, (const double*)lth_, g->dJ_dtheta_field);
     }
-    double h[8];
+    double h[kObjN + kPaccCols];
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h, sums_, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -372,12 +421,15 @@ class AdjointRun {
       g->J = h[2];
     else
       g->J = h[3];
-    g->dJ_dtheta = h[7];
-    for (int a = 0; a < 3; ++a) g->dJ_dg[a] = a < E.dim_ ? P.rho0 * h[4 + a] : 0.0;
+    g->dJ_dtheta = h[kObjN + kColTheta];
+    for (int a = 0; a < 3; ++a) g->dJ_dg[a] = a < E.dim_ ? P.rho0 * h[kObjN + a] : 0.0;
+    g->dJ_drho_in = P.bc == 1 ? h[kObjN + kColRhoIn] : 0.0;
+    g->dJ_drho_out = P.bc == 1 ? h[kObjN + kColRhoOut] : 0.0;
     g->ms_forward = ms1;
     g->ms_reverse = ms2;
     g->work_bytes = (int64_t)bytes_;
-    bool finite = std::isfinite(g->J) && std::isfinite(g->dJ_dtheta);
+    bool finite = std::isfinite(g->J) && std::isfinite(g->dJ_dtheta) && std::isfinite(g->dJ_drho_in) &&
+                  std::isfinite(g->dJ_drho_out);
     for (int a = 0; a < 3; ++a) finite = finite && std::isfinite(g->dJ_dg[a]);
     if (!finite) {
       E.err_ = "non-finite objective or gradient";

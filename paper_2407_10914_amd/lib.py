@@ -110,7 +110,7 @@ class AdjointSpec(C.Structure):
 class Gradients(C.Structure):
     _fields_ = [("J", C.c_double), ("dJ_dtheta", C.c_double), ("dJ_dg", C.c_double * 3),
                 ("dJ_dtheta_field", C.c_void_p), ("ms_forward", C.c_double), ("ms_reverse", C.c_double),
-                ("work_bytes", C.c_int64)]
+                ("work_bytes", C.c_int64), ("dJ_drho_in", C.c_double), ("dJ_drho_out", C.c_double)]
 
 
 _LIB = None

@@ -236,8 +236,9 @@ class Sim:
                 delta=0.0, field_grad=False):
         """Objective J of the state n_steps ahead and its exact discrete
         gradient with respect to the contact angle (global, per degree; and,
-        with field_grad, per voxel as a float64 CUDA tensor (nz, ny, nx)) and
-        the body-force acceleration.  The run's state is left unchanged."""
+        with field_grad, per voxel as a float64 CUDA tensor (nz, ny, nx)), the
+        body-force acceleration and, with Zou-He faces, the inlet and outlet
+        densities.  The run's state is left unchanged."""
         torch = _torch()
         sp = L.AdjointSpec()
         sp.objective = L.OBJECTIVES[objective] if isinstance(objective, str) else int(objective)
@@ -252,6 +253,7 @@ class Sim:
             gr.dJ_dtheta_field = field.data_ptr()
         L.check(L.load().cg_lbm_adjoint(self._h, C.byref(sp), C.byref(gr)))
         return {"J": gr.J, "dJ_dtheta": gr.dJ_dtheta, "dJ_dg": np.array(gr.dJ_dg[:]),
+                "dJ_drho_in": gr.dJ_drho_in, "dJ_drho_out": gr.dJ_drho_out,
                 "dJ_dtheta_field": field, "ms_forward": gr.ms_forward, "ms_reverse": gr.ms_reverse,
                 "work_bytes": gr.work_bytes}
 

@@ -1,0 +1,139 @@
+"""GPU adjoint of runs with Zou-He faces (Appendix B) against the oracle's
+forward-mode derivative of the same steps.
+
+The tube is short enough that a red slug sits against the outlet: the outlet
+plane holds mixed phase from the first steps, so the momentum split chi^s of
+Eqs. B.12-B.18 (with the upstream phase of Eq. 39) lies strictly between 0
+and 1, and the inlet injects a mixture (zeta_r = 0.25, Eq. B.1).  The
+objectives include the face layers (saturation over the whole tube, red
+volume next to the outlet, the momentum flux through the outlet, the inlet
+and an interior plane).  Parameters: the global contact angle, the per-voxel
+angle field along a random direction, the inlet and outlet densities, and
+the body force.  FP64 agrees with the oracle to rounding; FP32 to 1e-4."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2407_10914_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NZ = 14
+
+
+def outlet_tube(scheme=2, collision=1, zeta_r=0.25, g=(0.0, 0.0, 0.0), perturb=False):
+    """perturb: seeded +-0.05 noise on the phase, for single precision (a flat
+    interface across the tube makes the Scheme-II candidate choice an exact
+    tie at the wall nodes, which double and single precision may decide
+    differently)."""
+    c = inputs.tube(nx=10, ny=10, nz=NZ, radius=3.5, wet_len=4)
+    z = np.arange(NZ)[:, None, None]
+    phi0 = np.where((z >= 7) & (z < NZ - 1), 1.0, -1.0) * np.ones(c.solid.shape)
+    if perturb:
+        phi0 = np.clip(phi0 + 0.05 * np.random.default_rng(7).standard_normal(phi0.shape), -1.0, 1.0)
+    kw = dict(dim=3, periodic=c.periodic, tau_r=1.0, tau_b=0.7, sigma=0.02, beta=0.95, scheme=scheme,
+              theta_deg=60.0, bc=1, rho_in=1.04, rho_out=1.0, zeta_r=zeta_r, collision=collision, g=g)
+    return c.solid, phi0, kw
+
+
+def _sim(solid, prec, **kw):
+    from paper_2407_10914_amd.sim import Sim
+
+    return Sim(solid, precision=prec, **kw)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+OBJ = {"sat_nw": "saturation", "red_volume": "red_volume", "flux": "flux"}
+CASES = [("sat_nw", 0, NZ), ("red_volume", NZ - 4, NZ), ("flux", NZ - 1, 0), ("flux", 0, 0), ("flux", 6, 0)]
+
+
+@pytest.mark.parametrize("obj,lo,hi", CASES)
+def test_fp64_faces_match_the_oracle_tangent(obj, lo, hi):
+    solid, phi0, kw = outlet_tube()
+    steps = 20
+    o = O.OracleSim(solid, **kw)
+    ref = {sd: o.tangent(phi0, objective=obj, n_steps=steps, seed=sd, axis=2, lo=lo, hi=hi)
+           for sd in ("theta", "rho_in", "rho_out")}
+    s = _sim(solid, "f64", **kw)
+    s.set_phase(phi0)
+    r = s.adjoint(OBJ[obj], n_steps=steps, checkpoint_every=7, axis=2, lo=lo, hi=hi)
+    got = {"theta": r["dJ_dtheta"], "rho_in": r["dJ_drho_in"], "rho_out": r["dJ_drho_out"]}
+    for sd in ref:
+        print(f"{obj}[{lo},{hi}) {sd}: {got[sd]:.12e} / {ref[sd][1]:.12e}", flush=True)
+    J_t = ref["theta"][0]
+    assert rel(r["J"], J_t) <= 1e-13, (r["J"], J_t)
+    for sd in ref:
+        assert rel(got[sd], ref[sd][1]) <= 1e-9, (sd, got[sd], ref[sd][1])
+
+
+@pytest.mark.parametrize("scheme,collision", [(1, 0), (3, 1)])
+def test_fp64_faces_other_wetting_and_bgk(scheme, collision):
+    solid, phi0, kw = outlet_tube(scheme=scheme, collision=collision, zeta_r=0.0)
+    steps = 16
+    o = O.OracleSim(solid, **kw)
+    J_t, d_th = o.tangent(phi0, objective="sat_nw", n_steps=steps, seed="theta", axis=2, lo=0, hi=NZ)
+    _, d_in = o.tangent(phi0, objective="sat_nw", n_steps=steps, seed="rho_in", axis=2, lo=0, hi=NZ)
+    s = _sim(solid, "f64", **kw)
+    s.set_phase(phi0)
+    r = s.adjoint("saturation", n_steps=steps, checkpoint_every=5, axis=2, lo=0, hi=NZ)
+    print(f"scheme {scheme} collision {collision}: dtheta {r['dJ_dtheta']:.12e} / {d_th:.12e}; "
+          f"drho_in {r['dJ_drho_in']:.12e} / {d_in:.12e}", flush=True)
+    assert rel(r["J"], J_t) <= 1e-13
+    assert rel(r["dJ_dtheta"], d_th) <= 1e-9
+    assert rel(r["dJ_drho_in"], d_in) <= 1e-9
+
+
+def test_fp64_faces_theta_field_and_body_force():
+    solid, phi0, kw = outlet_tube(g=(0.0, 0.0, 2e-5))
+    steps = 16
+    th = np.where(solid == 1, 60.0, 0.0)
+    dirn = np.where(solid == 1, np.random.default_rng(3).standard_normal(solid.shape), 0.0)
+    o = O.OracleSim(solid, theta_field=th, **kw)
+    J_t, d_dir = o.tangent(phi0, objective="red_volume", n_steps=steps, seed="theta_field", theta_dir=dirn,
+                           axis=2, lo=NZ - 5, hi=NZ)
+    og = O.OracleSim(solid, **kw)
+    _, d_gz = og.tangent(phi0, objective="red_volume", n_steps=steps, seed="gz", axis=2, lo=NZ - 5, hi=NZ)
+    s = _sim(solid, "f64", theta_field=th, **kw)
+    s.set_phase(phi0)
+    r = s.adjoint("red_volume", n_steps=steps, checkpoint_every=6, axis=2, lo=NZ - 5, hi=NZ, field_grad=True)
+    grad = r["dJ_dtheta_field"].cpu().numpy()
+    g_dir = float((grad * dirn).sum())
+    s2 = _sim(solid, "f64", **kw)
+    s2.set_phase(phi0)
+    r2 = s2.adjoint("red_volume", n_steps=steps, checkpoint_every=6, axis=2, lo=NZ - 5, hi=NZ)
+    print(f"field {g_dir:.12e} / {d_dir:.12e}; dgz {r2['dJ_dg'][2]:.12e} / {d_gz:.12e}", flush=True)
+    assert rel(r["J"], J_t) <= 1e-13
+    assert rel(g_dir, d_dir) <= 1e-9
+    assert rel(float(grad.sum()), r["dJ_dtheta"]) <= 1e-10
+    assert rel(r2["dJ_dg"][2], d_gz) <= 1e-9
+
+
+@pytest.mark.parametrize("obj,lo,hi", [("sat_nw", 0, NZ), ("flux", NZ - 1, 0)])
+def test_fp32_faces_match_the_oracle_tangent(obj, lo, hi):
+    solid, phi0, kw = outlet_tube(perturb=True)
+    steps = 20
+    o = O.OracleSim(solid, eps="f32", **kw)
+    ref = {sd: o.tangent(phi0, objective=obj, n_steps=steps, seed=sd, axis=2, lo=lo, hi=hi)
+           for sd in ("theta", "rho_in", "rho_out")}
+    s = _sim(solid, "f32", **kw)
+    s.set_phase(phi0)
+    r = s.adjoint(OBJ[obj], n_steps=steps, checkpoint_every=7, axis=2, lo=lo, hi=hi)
+    got = {"theta": r["dJ_dtheta"], "rho_in": r["dJ_drho_in"], "rho_out": r["dJ_drho_out"]}
+    e = {sd: rel(got[sd], ref[sd][1]) for sd in ref}
+    print(f"fp32 {obj}: J {r['J']:.9e}/{ref['theta'][0]:.9e} rel {e}", flush=True)
+    assert rel(r["J"], ref["theta"][0]) <= 1e-6
+    for sd in ref:
+        assert e[sd] <= 1e-4, (sd, got[sd], ref[sd][1])
+
+
+def test_runs_without_faces_report_zero_density_gradients():
+    c = inputs.drop_periodic((12, 12, 12), 4.0)
+    s = _sim(c.solid, "f64", dim=3, periodic=c.periodic, tau_r=1.0, tau_b=0.8, sigma=0.01, beta=0.9, collision=1)
+    s.set_phase(c.phi0)
+    r = s.adjoint("red_volume", n_steps=3, axis=2, lo=0, hi=6)
+    assert r["dJ_drho_in"] == 0.0 and r["dJ_drho_out"] == 0.0
