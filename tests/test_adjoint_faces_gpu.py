@@ -137,3 +137,21 @@ def test_runs_without_faces_report_zero_density_gradients():
     s.set_phase(c.phi0)
     r = s.adjoint("red_volume", n_steps=3, axis=2, lo=0, hi=6)
     assert r["dJ_drho_in"] == 0.0 and r["dJ_drho_out"] == 0.0
+
+
+def test_autograd_hands_out_the_density_gradients():
+    from paper_2407_10914_amd.autograd import objective
+
+    solid, phi0, kw = outlet_tube()
+    s = _sim(solid, "f64", **kw)
+    rho = torch.tensor([1.04, 1.0], dtype=torch.float64, requires_grad=True)
+    th = torch.tensor(60.0, dtype=torch.float64, requires_grad=True)
+    J = objective(s, phi0, objective="saturation", n_steps=12, checkpoint_every=5, lo=0, hi=NZ, theta=th, rho=rho)
+    J.backward()
+    o = O.OracleSim(solid, **kw)
+    J_t, d_in = o.tangent(phi0, objective="sat_nw", n_steps=12, seed="rho_in", axis=2, lo=0, hi=NZ)
+    _, d_out = o.tangent(phi0, objective="sat_nw", n_steps=12, seed="rho_out", axis=2, lo=0, hi=NZ)
+    _, d_th = o.tangent(phi0, objective="sat_nw", n_steps=12, seed="theta", axis=2, lo=0, hi=NZ)
+    assert rel(float(J), J_t) <= 1e-13
+    assert rel(float(rho.grad[0]), d_in) <= 1e-9 and rel(float(rho.grad[1]), d_out) <= 1e-9
+    assert rel(float(th.grad), d_th) <= 1e-9
