@@ -155,3 +155,46 @@ def test_autograd_hands_out_the_density_gradients():
     assert rel(float(J.detach()), J_t) <= 1e-13
     assert rel(float(rho.grad[0]), d_in) <= 1e-9 and rel(float(rho.grad[1]), d_out) <= 1e-9
     assert rel(float(th.grad), d_th) <= 1e-9
+
+
+def rock_through_the_faces():
+    """A rock whose solid reaches both open faces (the face layers repeat the
+    layer next to them, so every outlet pore has a pore upstream): solid
+    boundary points in the face layers, read through clamped stencil links."""
+    c = inputs.grf_rock(n=20, nz=24, corr=3.0, porosity=0.35, seed=91, buffer=1)
+    solid = c.solid.copy()
+    solid[0] = solid[1]
+    solid[-1] = solid[-2]
+    nz = solid.shape[0]
+    zz = np.arange(nz)[:, None, None] * np.ones(solid.shape)
+    # red next to both faces: interfaces one and two layers in from them
+    phi0 = np.where((zz < 2) | (zz >= nz - 2), 1.0, -1.0)
+    kw = dict(dim=3, periodic=c.periodic, tau_r=1.0, tau_b=0.6, sigma=0.01, beta=0.95, scheme=1,
+              theta_deg=40.0, bc=1, rho_in=1.03, rho_out=1.0, zeta_r=1.0, collision=1)
+    return solid, phi0, kw
+
+
+@pytest.mark.parametrize("obj,lo,hi", [("sat_nw", 0, 24), ("flux", 23, 0)])
+def test_fp64_rock_through_the_faces_matches_the_oracle_tangent(obj, lo, hi):
+    solid, phi0, kw = rock_through_the_faces()
+    steps = 40
+    th = np.where(solid == 1, 40.0, 0.0)
+    dirn = np.where(solid == 1, np.random.default_rng(8).standard_normal(solid.shape), 0.0)
+    o = O.OracleSim(solid, theta_field=th, **kw)
+    J_t, d_dir = o.tangent(phi0, objective=obj, n_steps=steps, seed="theta_field", theta_dir=dirn, axis=2, lo=lo,
+                           hi=hi)
+    _, d_in = o.tangent(phi0, objective=obj, n_steps=steps, seed="rho_in", axis=2, lo=lo, hi=hi)
+    _, d_out = o.tangent(phi0, objective=obj, n_steps=steps, seed="rho_out", axis=2, lo=lo, hi=hi)
+    s = _sim(solid, "f64", theta_field=th, **kw)
+    s.set_phase(phi0)
+    r = s.adjoint(OBJ[obj], n_steps=steps, checkpoint_every=9, axis=2, lo=lo, hi=hi, field_grad=True)
+    grad = r["dJ_dtheta_field"].cpu().numpy()
+    g_dir = float((grad * dirn).sum())
+    print(f"rock {obj}: field {g_dir:.12e} / {d_dir:.12e}; rho_in {r['dJ_drho_in']:.12e} / {d_in:.12e}; "
+          f"rho_out {r['dJ_drho_out']:.12e} / {d_out:.12e}", flush=True)
+    # the face layers hold solid boundary points with a nonzero angle gradient
+    assert np.abs(grad[0]).max() > 0.0 and np.abs(grad[-1]).max() > 0.0
+    assert rel(r["J"], J_t) <= 1e-13
+    assert rel(g_dir, d_dir) <= 1e-9
+    assert rel(r["dJ_drho_in"], d_in) <= 1e-9
+    assert rel(r["dJ_drho_out"], d_out) <= 1e-9
