@@ -167,8 +167,18 @@ struct AdjBufs {
                        // (per degree), lambda rho_in, lambda rho_out
   double* lth;         // [V] sum over steps of lambda theta * idf at fluid boundary voxels
   Real* lpo;           // [n_out] lambda phi of each outlet node (its phase is the node's upstream, Eq. 39)
+  Real* ljt;           // [n_out] j^t of each outlet node's face (Eq. B.9), for ka_face
   int face_pull;       // the state of this step is a pulled one (the faces were applied to it)
 };
+
+// j^t of an outlet node from its pulled totals (canonical totals, or the
+// deviations g of the compact state, whose known weights sum to 1).
+template <bool kDev, class CT>
+__device__ __forceinline__ CT outlet_jt(const StepParams& P, const CT* ft) {
+  const CT S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
+  const CT T = ft[5] + ft[11] + ft[12] + ft[15] + ft[16];
+  return -(CT)(kDev ? P.rho_out - P.rho0 : P.rho_out) + (S + CT(2) * T);
+}
 
 // Columns of the per-block parameter sums.
 constexpr int kPaccCols = 6;
@@ -312,6 +322,7 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
       // them; rho^r is the post-face red sum (the node's phase is not its own)
       Real fr[Q];
       load_node<D>(in, G.nbr, n, fr, x);
+      if (fl & FL_OUT) A.ljt[n - (P.N - P.n_out)] = outlet_jt<true>(P, x);
       zou_he<true>(P, fl, (Real)phi_dec(R.phi[v]), fr, x);
       CT a = fr[0];
 #pragma unroll
@@ -355,7 +366,15 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
   } else {
     Real fr[Q], fx[Q];
     load_node<D>(in, G.nbr, n, fr, fx);
-    if constexpr (kFace) zou_he<false>(P, fl, (Real)phi_dec(R.phi[v]), fr, fx);
+    if constexpr (kFace) {
+      if (fl & FL_OUT) {
+        CT ft[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) ft[i] = fr[i] + fx[i];
+        A.ljt[n - (P.N - P.n_out)] = outlet_jt<false>(P, ft);
+      }
+      zou_he<false>(P, fl, (Real)phi_dec(R.phi[v]), fr, fx);
+    }
     CT a = fr[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) a = a + (CT)fr[i];
@@ -462,9 +481,11 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
     CT dl = CT(0), m = CT(0);
     if constexpr (!kSeed) {
       int li, ri;
-      // open: c_i leaves through an open face; zf: the pulled population it
-      // becomes is a +z one of an outlet node (adjoint L + 2 R^s there)
-      [[maybe_unused]] bool open = false;
+      // zf, the weight of R at the target: 2 for a pulled +z population of an
+      // outlet node, 0 for a -z one (an unknown of the face; the link it
+      // stands for left through the open face), 1 elsewhere.  A link that
+      // left through the inlet reads an unknown of the inlet node, whose L
+      // and R the face transpose set to zero.
       CT zf = CT(1);
       if constexpr (i == 0) {
         li = n;
@@ -480,10 +501,9 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
         li = row + ri;
         if constexpr (kFaces) {
           constexpr int ez = Lat<D>::e(i, 2);
-          open = s < kBounce;
           if constexpr (ez != 0) {
-            const bool up = ez > 0 ? s >= 0 : s == kBounce;
-            zf = (up && ri >= P.N - P.n_out) ? CT(2) : CT(1);
+            const CT zo = s >= 0 ? CT(1 + ez) : CT(1 - ez);
+            zf = ri >= P.N - P.n_out ? zo : CT(1);
           }
         }
       }
@@ -491,10 +511,6 @@ __device__ __forceinline__ void d_adj_node(const StepParams& P, const Geo<Real>&
       const Vec2<Real> r = A.lr[ri];
       dl = zf * ((CT)r.x - (CT)r.y);
       m = l + zf * (CT)r.y + ra * dl;
-      if constexpr (kFaces) {
-        dl = open ? CT(0) : dl;
-        m = open ? CT(0) : m;
-      }
     }
     a1 = a1 + bg[i] * dl;
     if constexpr (kMrt) {
@@ -1233,9 +1249,13 @@ __global__ void ka_seed_local(StepParams P, Geo<Real> G, Grids<Real> R, In in, A
 //           and phi_up (with the outlet node's own lambda phi, Eq. 39)
 //           passes to the upstream node's densities.
 // The node also adds its shares of dJ/drho_in and dJ/drho_out.
-template <class Real, int D, class In>
+// kStep: after a node stage, which left j^t of the outlet faces in ljt and the
+// upstream nodes' d phi / d rho^s in na; otherwise (the terminal condition of
+// a node-local objective) both are formed from the state's populations.
+template <class Real, int D, bool kStep, class In>
 __global__ void __launch_bounds__(256) ka_face(StepParams P, Geo<Real> G, Grids<Real> R, In in, Real* L,
-                                               Vec2<Real>* lr, const Real* lpo, double* pacc) {
+                                               Vec2<Real>* lr, const Real* lpo, const Real* ljt,
+                                               const Vec4<Real>* na, double* pacc) {
   constexpr int Q = Lat<D>::Q;
   constexpr bool kDev = sizeof(Real) == 4;
   using CT = Real;
@@ -1304,23 +1324,32 @@ __global__ void __launch_bounds__(256) ka_face(StepParams P, Geo<Real> G, Grids<
         o[11] = l[11] + CT(2) * lam + l[14];
         o[16] = l[16] + CT(2) * lam + l[17];
         o[15] = l[15] + CT(2) * lam + l[18];
-        // j^t from the pulled totals of x, and the upstream node's densities
-        Real fr[Q], fx[Q], rr, rb, rho;
-        adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
-        CT ft[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) ft[i] = kDev ? fx[i] : fr[i] + fx[i];
-        const CT S = ft[0] + ft[1] + ft[2] + ft[3] + ft[4] + ft[7] + ft[8] + ft[9] + ft[10];
-        const CT T = ft[5] + ft[11] + ft[12] + ft[15] + ft[16];
-        const CT jt = -(CT)(kDev ? P.rho_out - P.rho0 : P.rho_out) + (S + CT(2) * T);
-        const CT lphu = lpo[n - (P.N - P.n_out)] + CT(0.5) * jt * (Rb - Rr);
+        // j^t of the face, and d phi / d rho^s of the upstream node u
+        const int slot = n - (P.N - P.n_out);
         const int u = G.nbr.template get<kDirZp>(n);
-        load_outlet_upstream<D>(in, G.nbr, n, fr, fx);
-        adj_sums<Real, D>(P, fr, fx, rr, rb, rho);
-        const CT ir = CT(1) / rho;
+        CT jt, dru, dbu;
+        if constexpr (kStep) {
+          jt = ljt[slot];
+          const Vec4<Real> nu = na[u];
+          dru = nu.z;
+          dbu = nu.w;
+        } else {
+          Real fr[Q], fx[Q], rr, rb, rho;
+          adj_load<Real, D>(P, G, in, n, fr, fx, rr, rb, rho);
+          CT ft[Q];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) ft[i] = kDev ? fx[i] : fr[i] + fx[i];
+          jt = outlet_jt<kDev>(P, ft);
+          load_outlet_upstream<D>(in, G.nbr, n, fr, fx);
+          adj_sums<Real, D>(P, fr, fx, rr, rb, rho);
+          const CT ir = CT(1) / rho;
+          dru = CT(2) * rb * ir * ir;
+          dbu = CT(-2) * rr * ir * ir;
+        }
+        const CT lphu = lpo[slot] + CT(0.5) * jt * (Rb - Rr);
         Vec2<Real> ru = lr[u];
-        ru.x = ru.x + lphu * (CT(2) * rb * ir * ir);
-        ru.y = ru.y + lphu * (CT(-2) * rr * ir * ir);
+        ru.x = ru.x + lphu * dru;
+        ru.y = ru.y + lphu * dbu;
         lr[u] = ru;
       }
 #pragma unroll

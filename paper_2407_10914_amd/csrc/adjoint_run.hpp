@@ -63,6 +63,7 @@ class AdjointRun {
   double* pacc_ = nullptr;
   int npacc_ = 0;  // rows of pacc_
   Real* lpo_ = nullptr;  // lambda phi of the outlet nodes (Zou-He runs)
+  Real* ljt_ = nullptr;  // j^t of the outlet faces (Zou-He runs)
   int face_pull_ = 0;    // the state of the current step is pulled and has face nodes
   // front fields (phase, normal, colour gradient, force) of the state at
   // t0 + k for each ring index k, kept from the recomputation so the reverse
@@ -110,8 +111,8 @@ class AdjointRun {
     return e;
   }
   AdjBufs<Real> bufs() const {
-    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_,   na_,  lcf_,  lk_, ln_,
-                         lc_,     lphi_,       iden_, idf_, pacc_, lth_, lpo_, face_pull_};
+    return AdjBufs<Real>{lf_[p_], lf_[p_ ^ 1], lr_,   na_,  lcf_,  lk_,  ln_,
+                         lc_,     lphi_,       iden_, idf_, pacc_, lth_, lpo_, ljt_, face_pull_};
   }
 
   // one forward step from `in` into slot `out`; the front fields go to the
@@ -184,13 +185,20 @@ class AdjointRun {
         E.launch(-1, ka_face_node<Real, D, kSeed, false, In>, nt, P, E.G_, R, in, bufs(), AP_);
     }
   }
-  // the transpose of the faces on the adjoint just formed (lf_[p_], lr_)
+  // the transpose of the faces on the adjoint just formed (lf_[p_], lr_);
+  // after_node: a node stage of this state ran (ljt_ and na_ are its)
   template <int D, class In>
-  void face_transpose(const In& in, const Grids<Real>& R) {
+  void face_transpose(const In& in, const Grids<Real>& R, bool after_node) {
     const StepParams& P = E.P_;
-    if constexpr (D == 3 && In::kPull)
-      E.launch(-1, ka_face<Real, D, In>, 64 * face_tiles(P), P, E.G_, R, in, lf_[p_], lr_, (const Real*)lpo_,
-               pacc_);
+    if constexpr (D == 3 && In::kPull) {
+      const int nt = 64 * face_tiles(P);
+      if (after_node)
+        E.launch(-1, ka_face<Real, D, true, In>, nt, P, E.G_, R, in, lf_[p_], lr_, (const Real*)lpo_,
+                 (const Real*)ljt_, (const V4*)na_, pacc_);
+      else
+        E.launch(-1, ka_face<Real, D, false, In>, nt, P, E.G_, R, in, lf_[p_], lr_, (const Real*)lpo_,
+                 (const Real*)ljt_, (const V4*)na_, pacc_);
+    }
   }
 
   // lambda_{t} from lambda_{t+1}, the state at t being `in` (ring index k).
@@ -209,7 +217,7 @@ class AdjointRun {
     face_pull_ = faces_of<D>(in) ? 1 : 0;
     node_stage<D, false>(in, R);
     reverse_tail<D>(R);
-    if (face_pull_ && !first) face_transpose<D>(in, R);
+    if (face_pull_ && !first) face_transpose<D>(in, R, true);
   }
 
   // objective of the state `in` (into sums_) and the terminal adjoint
@@ -230,7 +238,7 @@ class AdjointRun {
       if (face_pull_ && P.n_out > 0)
         E.launch(-1, ka_fill<Real, Real>, P.n_out, (size_t)P.n_out, lpo_, Real(0));
     }
-    if (face_pull_) face_transpose<D>(in, E.R_);
+    if (face_pull_) face_transpose<D>(in, E.R_, AP_.objective == 2);
   }
 
   template <int D>
@@ -290,8 +298,9 @@ class AdjointRun {
     part_ = (double*)get(sizeof(double) * 4 * (size_t)(nb + 1));
     sums_ = (double*)get(sizeof(double) * (kObjN + kPaccCols));
     lpo_ = (Real*)get(sizeof(Real) * (size_t)std::max(1, P.n_out));
+    ljt_ = (Real*)get(sizeof(Real) * (size_t)std::max(1, P.n_out));
     ok = ok && lf_[0] && lf_[1] && lr_ && na_ && lcf_ && lk_ && ln_ && lc_ && lphi_ && iden_ && idf_ && lth_ &&
-         pacc_ && part_ && sums_ && lpo_;
+         pacc_ && part_ && sums_ && lpo_ && ljt_;
     if (!ok) {
       E.err_ = "device allocation for the adjoint failed";
       return CG_ENOMEM;
@@ -311,6 +320,7 @@ class AdjointRun {
     zero(lr_, sizeof(V2) * Np);
     zero(sums_, sizeof(double) * (kObjN + kPaccCols));
     zero(lpo_, sizeof(Real) * (size_t)std::max(1, P.n_out));
+    zero(ljt_, sizeof(Real) * (size_t)std::max(1, P.n_out));
     // grid voxels that no stage writes (interior solid) are read as zeros
     for (auto& x : fg_) {
       if (e == hipSuccess) e = Engine<Real>::fill_phi_zero(x.phi, V, st);
