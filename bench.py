@@ -196,12 +196,33 @@ def batched_leg(steps, warmup, count=64, ref_edge=256):
             "ratio": round(batched / single, 4), "tuning": report}
 
 
-def adjoint_leg(n_steps=2000, K=100, n=128):
+def adjoint_k_for_memory(info, n_steps, free_bytes, share=0.7):
+    """The largest checkpoint interval K <= n_steps whose device memory fits in
+    `share` of the free bytes: per state of the ring one state copy and its
+    kept front fields (phase and normal grids per voxel, C and force per
+    node; FP32 sizes), n_steps/K checkpoints, and the adjoint's own fields
+    (about six state copies).  K >= n_steps keeps every state of the forward
+    sweep, so the reverse sweep recomputes nothing."""
+    V, Np = info["voxels"], (info["fluid"] + 255) // 256 * 256
+    front = V * (4 + 12) + Np * (12 + 16)
+    st = info["state_bytes"]
+    budget = share * free_bytes - 6 * st
+    for K in range(n_steps, 0, -1):
+        need = K * (st + front) + (-(-n_steps // K) - 1 + 2) * st
+        if need <= budget:
+            return K
+    return 1
+
+
+def adjoint_leg(n_steps=2000, K=0, n=128, K_ref=100):
     """Adjoint through drainage: the 128^3 Gaussian-random-field rock (porosity
     0.22, z periodic, non-wetting fluid in the inlet buffer, body force 1e-5
     along z), a per-voxel contact-angle field of 40 deg on the solid, FP32
     MRT Scheme-I; objective = non-wetting mass saturation of the rock region
-    after n_steps; checkpoints every K steps.  The forward step time is taken
+    after n_steps.  Checkpoints every K steps; K = 0 takes the largest K that
+    the device's free memory holds (up to n_steps: then the forward sweep keeps
+    every state and the reverse sweep recomputes nothing), and the same call
+    is also timed with K_ref for comparison.  The forward step time is taken
     on the same run by plain stepping."""
     import torch
 
@@ -232,9 +253,24 @@ def adjoint_leg(n_steps=2000, K=100, n=128):
     fwd_ms = e0.elapsed_time(e1) / n_steps
     sim.set_phase(case.phi0)
     sim.adjoint("saturation", n_steps=4, checkpoint_every=2, lo=buf, hi=nz - buf, field_grad=True)  # warm-up
-    t0 = time.perf_counter()
-    r = sim.adjoint("saturation", n_steps=n_steps, checkpoint_every=K, lo=buf, hi=nz - buf, field_grad=True)
-    wall = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if K <= 0:
+        K = adjoint_k_for_memory(sim.info(), n_steps, free)
+
+    def timed(k):
+        sim.set_phase(case.phi0)
+        t0 = time.perf_counter()
+        r = sim.adjoint("saturation", n_steps=n_steps, checkpoint_every=k, lo=buf, hi=nz - buf, field_grad=True)
+        return r, time.perf_counter() - t0
+
+    try:
+        r, wall = timed(K)
+    except Exception as e:  # the memory estimate was too optimistic: the reference interval
+        print(f"# adjoint with K = {K} failed ({e}); K = {K_ref}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        K, K_ref = K_ref, 0
+        r, wall = timed(K)
     gf = r["dJ_dtheta_field"]
     out = {"workload": f"{n}^3 drainage rock, FP32 MRT Scheme-I, theta(x) = 40 deg, g_z = 1e-5, "
                        f"objective S_nw (rock region) after {n_steps} steps, checkpoint every {K}",
@@ -244,8 +280,23 @@ def adjoint_leg(n_steps=2000, K=100, n=128):
            "adjoint_reverse_ms": round(r["ms_reverse"], 2),
            "ratio_reverse_to_forward": round(r["ms_reverse"] / (n_steps * fwd_ms), 4),
            "ratio_total_to_forward": round((r["ms_forward"] + r["ms_reverse"]) / (n_steps * fwd_ms), 4),
-           "wall_s": round(wall, 3), "work_gb": round(r["work_bytes"] / 1e9, 3)}
-    del gf, r, sim
+           "wall_s": round(wall, 3), "work_gb": round(r["work_bytes"] / 1e9, 3),
+           "device_free_gb_before": round(free / 1e9, 1)}
+    J0, d0 = r["J"], r["dJ_dtheta"]
+    del gf, r
+    torch.cuda.empty_cache()
+    if K_ref and K_ref != K:
+        r, wall = timed(K_ref)
+        out["with_K_ref"] = {"K": K_ref, "adjoint_forward_sweep_ms": round(r["ms_forward"], 2),
+                             "adjoint_reverse_ms": round(r["ms_reverse"], 2),
+                             "ratio_reverse_to_forward": round(r["ms_reverse"] / (n_steps * fwd_ms), 4),
+                             "ratio_total_to_forward": round((r["ms_forward"] + r["ms_reverse"]) / (n_steps * fwd_ms),
+                                                             4),
+                             "work_gb": round(r["work_bytes"] / 1e9, 3),
+                             "same_J": r["J"] == J0, "same_dJ_dtheta": r["dJ_dtheta"] == d0}
+        del r
+        torch.cuda.empty_cache()
+    del sim
     torch.cuda.empty_cache()
     return out
 
@@ -266,7 +317,8 @@ def main():
                          "every tenth of it (0: off)")
     ap.add_argument("--no-tune", action="store_true", help="keep 256 threads per block for every kernel")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
-    ap.add_argument("--adjoint-k", type=int, default=100)
+    ap.add_argument("--adjoint-k", type=int, default=0,
+                    help="checkpoint interval of the adjoint leg (0: the largest that free device memory holds)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run the library's plain 1 GiB copy kernel (reference for the HBM byte counters)")
     ap.add_argument("--windows", type=int, default=5, help="timed windows the --steps are split into (median)")

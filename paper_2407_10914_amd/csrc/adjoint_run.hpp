@@ -1,7 +1,11 @@
 // Host side of the discrete adjoint: forward sweep with checkpoints every K
 // steps, then segment by segment (last first) the K states of the segment are
 // recomputed from its checkpoint into a ring of state buffers and the reverse
-// steps run from the last state of the segment down to its checkpoint.
+// steps run from the last state of the segment down to its checkpoint.  The
+// segments are counted from the end (the first one holds the remainder), so
+// the last segment, whose states and front fields the forward sweep keeps
+// and which is not recomputed, is always a full one: with memory for K near
+// n_steps almost nothing is recomputed.
 // Included at the end of engine.hpp (needs the complete Engine).
 #pragma once
 
@@ -248,7 +252,14 @@ class AdjointRun {
     const int64_t T = sp.n_steps;
     const int64_t K = std::min<int64_t>(sp.checkpoint_every, T);
     const int64_t nseg = (T + K - 1) / K;
-    const int64_t Llast = T - (nseg - 1) * K;
+    // segment 0 holds the remainder L0 (1..K), every later one K steps;
+    // checkpoint c (c >= 1) is the state at the start of segment c
+    const int64_t L0 = T - (nseg - 1) * K;
+    auto seg_len = [&](int64_t c) { return c == 0 ? L0 : K; };
+    const int64_t t_last = nseg > 1 ? L0 + (nseg - 2) * K : 0;  // start of the last segment
+    const int64_t Llast = seg_len(nseg - 1);
+    auto is_ck = [&](int64_t t) { return t >= L0 && t <= t_last && t > 0 && (t - L0) % K == 0; };
+    auto ck_of = [&](int64_t t) { return (size_t)((t - L0) / K); };
     // state buffers: checkpoints 1..nseg-1, two temporaries, the ring of K
     std::vector<Slot> ck((size_t)(nseg - 1)), tmp(2), ring((size_t)K);
     bool ok = true;
@@ -368,15 +379,15 @@ class AdjointRun {
         f(in_of<D>(ring[(size_t)(k - 1)]));
     };
 
-    // forward sweep: checkpoints at t = cK; the last segment's states go to the ring
-    const int64_t t_last = (nseg - 1) * K;
+    // forward sweep: the checkpoints at the segment starts; the last
+    // segment's states (and front fields) go to the ring
     for (int64_t t = 0; t < T; ++t) {
       const int64_t t1 = t + 1;
       Slot out;
       if (t1 > t_last)
         out = ring[(size_t)(t1 - t_last - 1)];
-      else if (t1 % K == 0)
-        out = ck[(size_t)(t1 / K - 1)];
+      else if (is_ck(t1))
+        out = ck[ck_of(t1)];
       else
         out = tmp[(size_t)(t1 & 1)];
       const int64_t kg = t >= t_last ? t - t_last : -1;
@@ -384,8 +395,8 @@ class AdjointRun {
         with_ck(0, [&](const auto& in) { fstep<D>(in, out, kg); });
       } else if (t > t_last) {
         fstep<D>(in_of<D>(ring[(size_t)(t - t_last - 1)]), out, kg);
-      } else if (t % K == 0) {
-        fstep<D>(in_of<D>(ck[(size_t)(t / K - 1)]), out, kg);
+      } else if (is_ck(t)) {
+        fstep<D>(in_of<D>(ck[ck_of(t)]), out, kg);
       } else {
         fstep<D>(in_of<D>(tmp[(size_t)(t & 1)]), out);
       }
@@ -396,7 +407,7 @@ class AdjointRun {
     with_seg(nseg - 1, Llast, [&](const auto& in) { terminal<D>(in); });
     // reverse sweep
     for (int64_t c = nseg - 1; c >= 0; --c) {
-      const int64_t L = c == nseg - 1 ? Llast : K;
+      const int64_t L = seg_len(c);
       if (c != nseg - 1) {
         for (int64_t k = 0; k < L; ++k)
           with_seg(c, k, [&](const auto& in) { fstep<D>(in, ring[(size_t)k], k); });
