@@ -396,10 +396,13 @@ cg_status cg_lbm_drop_shape(cg_lbm* h, int base_axis, int wall_axis, int slice, 
  * With the fictitious-density model the angle enters through the fixed phase
  * -cos(theta) of each solid boundary point (Eq. 24), so the field gradient
  * sits on those points' own voxels.
- * The forward sweep stores the state every checkpoint_every = K steps; the
- * reverse sweep recomputes the K states of one segment at a time into a ring
- * of K state buffers, so the device memory held during the call is about
- * (n_steps/K + K + 2) state copies (cg_info.state_bytes each) plus the adjoint
+ * The forward sweep stores the state every checkpoint_every = K steps (the
+ * segments counted from the end, the first one holding the remainder) and
+ * keeps the last K states; the reverse sweep recomputes the states of each
+ * earlier segment into a ring of K state buffers, so the first n_steps - K
+ * states are computed twice (none with K >= n_steps) and the device memory
+ * held during the call is about (n_steps/K + K + 2) state copies
+ * (cg_info.state_bytes each, plus the front fields of K states) plus the adjoint
  * fields.  delta > 0 replaces |C| by max(|C|, delta) in the Jacobian of
  * n = C/|C| (Eq. 27) only; the forward arithmetic is unchanged; 0 keeps the
  * exact derivative.  Every boundary of the step is covered: closed and
