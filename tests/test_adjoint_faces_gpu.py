@@ -198,3 +198,23 @@ def test_fp64_rock_through_the_faces_matches_the_oracle_tangent(obj, lo, hi):
     assert rel(g_dir, d_dir) <= 1e-9
     assert rel(r["dJ_drho_in"], d_in) <= 1e-9
     assert rel(r["dJ_drho_out"], d_out) <= 1e-9
+
+
+@pytest.mark.parametrize("steps,K", [(1, 1), (2, 1), (2, 5), (3, 2)])
+def test_fp64_faces_few_steps(steps, K):
+    """The shortest runs: the terminal condition's face transpose alone (one
+    step), and one or two reverse steps after it, with checkpoint intervals
+    below and above the run's length."""
+    solid, phi0, kw = outlet_tube()
+    o = O.OracleSim(solid, **kw)
+    for obj, lo, hi in (("sat_nw", 0, NZ), ("flux", NZ - 1, 0)):
+        ref = {sd: o.tangent(phi0, objective=obj, n_steps=steps, seed=sd, axis=2, lo=lo, hi=hi)
+               for sd in ("theta", "rho_in", "rho_out")}
+        s = _sim(solid, "f64", **kw)
+        s.set_phase(phi0)
+        r = s.adjoint(OBJ[obj], n_steps=steps, checkpoint_every=K, axis=2, lo=lo, hi=hi)
+        got = {"theta": r["dJ_dtheta"], "rho_in": r["dJ_drho_in"], "rho_out": r["dJ_drho_out"]}
+        assert rel(r["J"], ref["theta"][0]) <= 1e-13
+        for sd in ref:
+            d = ref[sd][1]
+            assert abs(got[sd] - d) <= 1e-9 * max(abs(d), 1e-12), (obj, sd, got[sd], d)
