@@ -792,8 +792,22 @@ class Engine final : public EngineBase {
   // solid (4), curvature and force (5)
   template <int D, class In>
   void front_with(const In& in, int upto) {
-    phase_with<D>(in, true);
-    if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
+    if constexpr (std::is_same_v<In, InCompact<D>>) {
+      if (upto >= 2 && nsb_ && P_.n_in + P_.n_out > 0) {
+        // the face stage rides in the solid-boundary phase launch
+        launch(K_PHASE, k_phase<Real, D, In>, P_.N, P_, G_, R_, in);
+        const int bs = bs_[K_SB_PHI];
+        const int nfb = ((64 * face_tiles(P_) + bs - 1) / bs + 7) / 8 * 8;
+        const int nsbb = (nsb_ + bs - 1) / bs;
+        launch_bs(K_SB_PHI, bs, k_face_sb_phi<Real, D, In>, (nfb + nsbb) * bs, P_, G_, R_, in, nfb);
+      } else {
+        phase_with<D>(in, true);
+        if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
+      }
+    } else {
+      phase_with<D>(in, true);
+      if (upto >= 2 && nsb_) launch(K_SB_PHI, k_sb_phi<Real, D>, nsb_, P_, G_, R_);
+    }
     if (upto >= 3) launch(K_NORMAL, k_normal<Real, D>, P_.N, P_, G_, R_);
     if (upto >= 4 && nsb_) launch(K_SB_N, k_sb_n<Real, D>, nsb_, P_, G_, R_);
     if (upto >= 5) launch(K_CURV, k_curv<Real, D>, P_.N, P_, G_, R_);

@@ -199,6 +199,17 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
   nb_all<D>(P, ps, nbi);
   using PhiT = typename Grids<Real>::PhiT;
   const auto rs = grid_rsrc(R.phi, sizeof(PhiT) * (size_t)P.V);
+  // a fluid voxel of the outlet layer is an outlet node, whose phase is the
+  // node upstream's (Eq. 39): read there, so this stage does not wait for the
+  // copy the face stage makes (the two share a launch)
+  if (P.n_out > 0) {
+    const int first_out = P.V - P.nx * P.ny;
+    unroll<Q - 1>([&](auto I) {
+      constexpr int i = I + 1;
+      if constexpr (D == 3 && Lat<D>::e(i, 2) >= 0)
+        nbi[i] = nbi[i] >= first_out ? nbi[i] - P.nx * P.ny : nbi[i];
+    });
+  }
   double ph[Q];
   unroll<Q - 1>([&](auto I) {
     constexpr int i = I + 1;
@@ -220,6 +231,21 @@ __device__ __forceinline__ void d_sb_phi(const StepParams& P, const Geo<Real>& G
 template <class Real, int D>
 __global__ void k_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R) {
   d_sb_phi<Real, D>(P, G, R, node_id());
+}
+
+// The face stage and the solid-boundary phase stage in one launch (both need
+// only the phase stage): the first nfb blocks cover the face tiles, the rest
+// the solid boundary points with the XCD-aware mapping of their own range
+// (nfb is a multiple of 8, so block b of that range runs on XCD b mod 8).
+template <class Real, int D, class In>
+__global__ void k_face_sb_phi(StepParams P, Geo<Real> G, Grids<Real> R, In in, int nfb) {
+  if ((int)blockIdx.x < nfb) {
+    const int n = face_node(P, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+    if (n >= 0) d_face<Real, D, In>(P, G, R, in, n);
+  } else {
+    const int b = (int)blockIdx.x - nfb;
+    d_sb_phi<Real, D>(P, G, R, xcd_tile(b, (int)gridDim.x - nfb) * (int)blockDim.x + (int)threadIdx.x);
+  }
 }
 
 // ----------------------------------------------------------------- k_normal
