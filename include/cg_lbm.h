@@ -270,9 +270,11 @@ cg_status cg_lbm_load(cg_lbm* h, const void* src);
  * cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n, k_curv,
  * k_main, k_face; -1 = all, 0 = off).  A time step runs k_phase, k_sb_phi,
  * k_normal, k_sb_n and k_main (which evaluates the curvature and force of its
- * node); a single-precision run with Zou-He faces also runs k_face (the
- * faces' unknowns at the face nodes) after k_phase; k_curv stores the
- * curvature and force for the reverse steps of the adjoint.
+ * node); in a single-precision run with Zou-He faces the face stage (the
+ * outlet's upstream phase, the faces' unknowns at the face nodes) shares the
+ * k_sb_phi launch and is timed with it; k_face counts its launches of its
+ * own (state export and staging); k_curv stores the curvature and force for
+ * the reverse steps of the adjoint.
  * cg_lbm_kernel_times synchronises, then reports for each kernel its name,
  * launch count and total milliseconds since the last reset (n: in =
  * capacity, out = count). */
