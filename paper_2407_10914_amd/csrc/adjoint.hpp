@@ -887,11 +887,19 @@ __device__ __forceinline__ void d_adj_curv(const StepParams& P, const Geo<Real>&
   A.ln[v] = o;
 }
 
-// Separate launches for the fluid nodes and the solid boundary points (one
-// launch over both lists measured slower: 56 us against 28 + 17 us at 128^3).
-template <class Real, int D, bool kSb>
-__global__ void ka_curv(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A) {
-  d_adj_curv<Real, D, kSb>(P, G, R, A, node_id_plain());
+// The fluid nodes and the solid boundary points in one launch: the first nfb
+// blocks take the fluid nodes, the others the solid boundary points, so each
+// block runs one of the two code paths and the short solid-boundary part
+// overlaps the tail of the fluid part (the two write disjoint voxels and
+// read only what the node stage wrote).  A launch over both lists with the
+// choice made per thread measured slower than two launches (56 against
+// 28 + 17 us at 128^3); this split per block saves about 5 us per step.
+template <class Real, int D>
+__global__ void ka_curv(StepParams P, Geo<Real> G, Grids<Real> R, AdjBufs<Real> A, int nfb) {
+  if ((int)blockIdx.x < nfb)
+    d_adj_curv<Real, D, false>(P, G, R, A, node_id_plain());
+  else
+    d_adj_curv<Real, D, true>(P, G, R, A, ((int)blockIdx.x - nfb) * (int)blockDim.x + (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------- ka_normal

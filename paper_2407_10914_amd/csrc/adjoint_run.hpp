@@ -140,8 +140,8 @@ class AdjointRun {
   void reverse_tail(const Grids<Real>& R) {
     const StepParams& P = E.P_;
     const AdjBufs<Real> A = bufs();
-    E.launch(-1, ka_curv<Real, D, false>, P.N, P, E.G_, R, A);
-    if (P.nsb) E.launch(-1, ka_curv<Real, D, true>, P.nsb, P, E.G_, R, A);
+    const int nfb = (P.N + BS - 1) / BS, nsbb = (P.nsb + BS - 1) / BS;
+    E.launch_bs(-1, BS, ka_curv<Real, D>, (nfb + nsbb) * BS, P, E.G_, R, A, nfb);
     E.launch(-1, ka_normal<Real, D>, P.N, P, E.G_, R, A, AP_);
     if (P.nsb) E.launch(-1, ka_sb_phi<Real, D>, P.nsb, P, E.G_, A);
     E.launch(-1, ka_phi<Real, D>, P.N, P, E.G_, A);
