@@ -265,8 +265,9 @@ int64_t cg_lbm_snapshot_bytes(const cg_lbm* h);
 cg_status cg_lbm_save(cg_lbm* h, void* dst);
 cg_status cg_lbm_load(cg_lbm* h, const void* src);
 
-/* Kernel timing: mask selects the kernels whose every launch is bracketed by
- * HIP events on the handle's stream (bit k = k-th kernel in the order
+/* Kernel timing: mask selects the kernels whose every launch carries HIP
+ * events on the handle's stream, attached to the dispatch (hipExtLaunchKernel),
+ * so that they time the kernel's own start and end (bit k = k-th kernel in the order
  * cg_lbm_kernel_times reports: k_phase, k_sb_phi, k_normal, k_sb_n, k_curv,
  * k_main, k_face; -1 = all, 0 = off).  A time step runs k_phase, k_sb_phi,
  * k_normal, k_sb_n and k_main (which evaluates the curvature and force of its
@@ -294,7 +295,7 @@ cg_status cg_lbm_kernel_times(cg_lbm* h, char (*names)[32], int64_t* counts, dou
 cg_status cg_lbm_reset_timing(cg_lbm* h);
 
 /* Block-size autotuner of one run: times reps steps with every kernel at 64,
- * then 128, then 256 threads per block (HIP events around each launch) and
+ * then 128, then 256 threads per block (the kernel timers' events) and
  * keeps the fastest size per kernel for the run's later steps.  Advances the
  * run by 3 * reps steps (tune before taking the steps that matter).  report
  * (may be NULL) receives the choice and the times. */

@@ -4,6 +4,7 @@
 // own translation units (different floating-point contraction flags).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -746,16 +747,15 @@ class Engine final : public EngineBase {
   void launch_bs(int kid, int bs, K kern, int nthreads, Args... args) {
     if (nthreads <= 0) return;
     const int nb = (nthreads + bs - 1) / bs;
-    hipEvent_t a = nullptr, b = nullptr;
     const bool tm = kid >= 0 && (timing_ & (1 << kid));
-    if (tm) {
-      a = get_event();
-      b = get_event();
-      (void)hipEventRecord(a, stream_);
-    }
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), 0, stream_, args...);
-    if (tm) {
-      (void)hipEventRecord(b, stream_);
+    if (!tm) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), 0, stream_, args...);
+    } else {
+      // events attached to the dispatch itself (its start and end), not
+      // recorded as commands of their own around it, which would add the
+      // queue's few microseconds between commands to every launch
+      hipEvent_t a = get_event(), b = get_event();
+      hipExtLaunchKernelGGL(kern, dim3(nb), dim3(bs), 0, stream_, a, b, 0u, args...);
       recs_.push_back({kid, a, b});
       if (recs_.size() > 4096) {
         (void)hipStreamSynchronize(stream_);
