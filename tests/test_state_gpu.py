@@ -6,7 +6,8 @@ not load into a run of another geometry or precision; canonical populations
 exported from an FP64 run and imported into a fresh one (host or device
 buffers) continue bit for bit; the Scheme-I line option LITERAL agrees with
 the oracle as the default rule does; the kernel timers count every launch of
-the kernels they are set for.
+the kernels they are set for, and their durations fit inside the stream time
+of the steps they time.
 """
 import dataclasses
 import sys
@@ -152,3 +153,32 @@ def test_kernel_timing_counts_every_launch():
     s.set_timing(None)
     s.step(1)
     assert s.kernel_times()["k_main"][0] == 2
+
+
+def test_kernel_timers_fit_inside_the_stream_time():
+    """The timers' events belong to the dispatches: over timed steps on one
+    stream the kernels run one after another, so their summed durations fit
+    inside the elapsed time of the same steps measured around them.  (On
+    small grids the host's launch rate, not the kernels, sets that time.)"""
+    import torch
+
+    case, kw = rock(n=96, buffer=4)
+    s = _sim(case, kw, "f32")
+    s.step(3)
+    s.sync()
+    s.set_timing("all")
+    s.reset_timing()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    s.step(20)
+    e1.record(st)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = e0.elapsed_time(e1)
+    t = s.kernel_times()
+    s.set_timing(None)
+    busy = sum(ms for _, ms in t.values())
+    _say(f"kernels {busy:.4f} ms inside {wall:.4f} ms", t)
+    assert t["k_main"][0] == 20 and t["k_phase"][0] == 20
+    assert 0.1 * wall <= busy <= wall
