@@ -103,8 +103,10 @@ def _batch(sims):
     return Batch(sims)
 
 
-def laplace_sweep(n=128, radii=(10.0, 14.0, 18.0, 22.0, 26.0, 30.0), steps=10000, sigma=1.0 / 45.0, tau_r=1.0,
+def laplace_sweep(n=128, radii=(10.0, 14.0, 18.0, 22.0, 26.0, 30.0), steps=40000, sigma=1.0 / 45.0, tau_r=1.0,
                   tau_b=0.6, beta=0.95, precision="f32", log=None):
+    # 40000 steps: the largest drop relaxes on the viscous time R^2/nu, about
+    # 27000 steps at R = 30 (at 10000 its pressure jump is still moving)
     from . import inputs
     from .sim import Sim
 
@@ -263,7 +265,7 @@ def main(argv=None):
     ap.add_argument("--json", default=None)
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--steps", type=int, default=None,
-                    help="steps of the Laplace and contact-angle runs (default 10000 and 20000)")
+                    help="steps of the Laplace and contact-angle runs (default 40000 and 20000)")
     ap.add_argument("--schemes", default=None,
                     help="wetting schemes of the contact-angle sweep, e.g. 1,2,3 (3: fictitious density, Eq. 24)")
     a = ap.parse_args(argv)
