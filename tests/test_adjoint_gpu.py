@@ -72,6 +72,32 @@ def test_fp64_2d_matches_oracle_tangent(obj, lo, hi):
     assert rel(r["dJ_dg"][0], d_gx) <= 1e-9
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_wall_free_periodic_drop_matches_oracle_tangent(prec, tol):
+    """A run with no solid voxel at all (fully periodic 3D box, so no fluid or
+    solid boundary point: the solid-boundary reverse stages have nothing to
+    do): dJ/dg against the oracle's tangent, and dJ/dtheta exactly 0 since
+    no angle enters the step."""
+    n = 14
+    solid = np.zeros((n, n, n), np.uint8)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((x - 6.3) ** 2 + (y - 7.1) ** 2 + (z - 5.6) ** 2)
+    phi0 = np.tanh(4.5 - r)
+    kw = dict(dim=3, periodic=(1, 1, 1), tau_r=1.0, tau_b=0.6, sigma=0.01, beta=0.95, scheme=1, theta_deg=50.0,
+              collision=1, g=(0.0, 0.0, 2e-5))
+    steps, lo, hi = 25, 7, 14
+    o = O.OracleSim(solid, **kw)
+    J_t, d_gz = o.tangent(phi0, objective="red_volume", n_steps=steps, seed="gz", axis=2, lo=lo, hi=hi)
+    s = _sim(solid, prec, **kw)
+    s.set_phase(phi0)
+    res = s.adjoint("red_volume", n_steps=steps, checkpoint_every=6, axis=2, lo=lo, hi=hi)
+    print(f"{prec}: J {res['J']:.15e} / {J_t:.15e}; dgz {res['dJ_dg'][2]:.12e} / {d_gz:.12e}; "
+          f"dtheta {res['dJ_dtheta']!r}", flush=True)
+    assert rel(res["J"], J_t) <= (1e-13 if prec == "f64" else 1e-6)
+    assert rel(res["dJ_dg"][2], d_gz) <= tol
+    assert res["dJ_dtheta"] == 0.0
+
+
 def test_checkpoint_interval_does_not_change_the_result():
     solid, phi0, kw = slug_2d()
     s = _sim(solid, "f64", **kw)
