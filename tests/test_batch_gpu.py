@@ -4,12 +4,13 @@ rounding of the same arithmetic), with or without the captured graph, before
 and after autotuning; and every run of a batch against its own oracle run
 (FP64: 1e-12, bitwise in practice; FP32: the one-step protocol from the
 batch's state), including two runs at the smallest edge of the batched
-contact-angle sweep (48^3, Scheme-I and Scheme-II)."""
+contact-angle sweep (48^3, Scheme-I and Scheme-II) and a periodic drop
+without walls."""
 import numpy as np
 import pytest
 
 import oracle as O
-from cases import c2_tube, rel, sessile_3d
+from cases import c2_tube, drop_3d, rel, sessile_3d
 from parity_helpers import TOL32, TOL64, compare_macro, say
 
 pytestmark = pytest.mark.gpu
@@ -29,11 +30,12 @@ def _runs(precision, specs):
 def _specs(sweep=False):
     # uneven sizes, both schemes, angles on both sides of 90 degrees, and one
     # run with Zou-He faces; with sweep, two runs of the batched sweep's
-    # smallest edge
+    # smallest edge and a periodic drop without any solid voxel (a run whose
+    # solid-boundary stages have no point)
     out = [sessile_3d(16, 40.0, 1), sessile_3d(20, 120.0, 2), sessile_3d(13, 75.0, 2),
            c2_tube(scheme=1, theta=45.0, drive="type1", nz=24, radius=6.0, wet_len=8)]
     if sweep:
-        out += [sessile_3d(48, 25.0, 1), sessile_3d(48, 150.0, 2)]
+        out += [sessile_3d(48, 25.0, 1), sessile_3d(48, 150.0, 2), drop_3d(n=14, R=4.5)]
     return out
 
 
