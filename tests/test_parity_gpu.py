@@ -233,6 +233,24 @@ def test_fp32_per_step_full_size_rock_in_the_benchmark_configuration():
     _compare_macro(g, o, case.solid == 0, TOL32, "rock256 fp32 step 60->61")
 
 
+def test_fp64_full_size_rock_in_the_benchmark_configuration():
+    """The benchmark's 256^3 rock (4.6 M fluid nodes, 8-bit pull table,
+    Type-I Zou-He, Scheme-I 30 deg, MRT) in the double-precision build, tuned
+    block sizes: bit for bit with the oracle after 12 steps (about 20 s of
+    oracle time on the host)."""
+    import bench
+
+    case, kw = bench.workload(256)
+    g = _sim(case, kw, "f64")
+    _say("rock256 fp64 tuning", g.tune(reps=1))
+    t = g.time
+    o = _orc(case, kw)
+    o.step(t)
+    g.step(12 - t)
+    o.step(12 - t)
+    _compare_macro(g, o, case.solid == 0, TOL64, "rock256 fp64 t=12")
+
+
 def test_fp32_against_fp64_observables_over_a_drainage_run_of_the_benchmark_rock():
     """The two builds run the benchmark's 256^3 drainage side by side for 2000
     steps (the FP64 build reproduces the oracle bit for bit on the smaller
