@@ -102,10 +102,11 @@ def cpu_baseline(case, kw, budget_s=20.0, threads=None):
                 hours_for_10k_steps=round(el / steps * 1e4 / 3600, 2))
 
 
-def fp64_leg(case, kw, steps=50, warmup=5):
+def fp64_leg(case, kw, steps=50, warmup=5, tune=True):
     """The same 256^3 step in double precision (the build that reproduces the
     oracle bit for bit): fluid-node MLUPS and k_main's algorithmic rate
-    (608 B per node), 256 threads per block."""
+    (608 B per node), block sizes from the run's tuner (256 threads per block
+    with tune=False)."""
     import torch
 
     from paper_2407_10914_amd.sim import Sim
@@ -113,6 +114,7 @@ def fp64_leg(case, kw, steps=50, warmup=5):
     sim = Sim(case.solid, precision="f64", **kw)
     sim.set_phase(case.phi0)
     n_fluid = sim.info()["fluid"]
+    report = sim.tune(reps=2) if tune else "256 threads per block"
     sim.step(warmup)
     sim.sync()
     sim.set_timing(["k_main"])
@@ -132,7 +134,8 @@ def fp64_leg(case, kw, steps=50, warmup=5):
     main_us = kms / max(cnt, 1) * 1e3
     return {"mlups": round(n_fluid * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 4),
             "k_main_us": round(main_us, 2),
-            "k_main_alg_gbs": round(2 * 19 * 2 * 8 * n_fluid / (main_us * 1e-6) / 1e9, 1), "steps": steps}
+            "k_main_alg_gbs": round(2 * 19 * 2 * 8 * n_fluid / (main_us * 1e-6) / 1e9, 1), "steps": steps,
+            "tuning": report}
 
 
 def batched_leg(steps, warmup, count=64, ref_edge=256):
@@ -442,7 +445,7 @@ def main():
         del x, y
     f64 = None
     if not args.no_fp64:
-        f64 = fp64_leg(case, kw)
+        f64 = fp64_leg(case, kw, tune=not args.no_tune)
         print(f"# fp64: {f64}", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batch:
